@@ -1,0 +1,110 @@
+"""Pins for the oracle's noise: Philox4x32-10 words against an independent
+library implementation (PyTorch's host Philox engine header), and the
+distribution of the Box-Muller normals (Sec. 2.1.3 asks for independent
+N(0, dt) increments)."""
+import ctypes
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.stats as st
+
+from oracle import particles as P
+
+_HELPER_SRC = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdint>
+extern "C" void torch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    uint64_t seed = (uint64_t)key[0] | ((uint64_t)key[1] << 32);
+    uint64_t subseq = (uint64_t)ctr[2] | ((uint64_t)ctr[3] << 32);
+    uint64_t offset = (uint64_t)ctr[0] | ((uint64_t)ctr[1] << 32);
+    at::philox_engine eng(seed, subseq, offset);
+    for (int i = 0; i < 4; ++i) out[i] = eng();
+}
+"""
+
+
+def _torch_philox_lib():
+    import torch
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    if not os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")) or not shutil.which("g++"):
+        pytest.skip("PyTorch Philox header or g++ not available")
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "h.cpp")
+    so = os.path.join(d, "h.so")
+    with open(src, "w") as f:
+        f.write(_HELPER_SRC)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-I", inc, "-o", so, src])
+    L = ctypes.CDLL(so)
+    L.torch_philox.argtypes = [ctypes.c_void_p] * 3
+    return L
+
+
+def test_philox_words_match_independent_library(oracle_lib):
+    L = _torch_philox_lib()
+    rng = np.random.default_rng(1234)
+    cases = [np.zeros(4, np.uint32), np.full(4, 0xFFFFFFFF, np.uint32)]
+    cases += [rng.integers(0, 2 ** 32, 4, dtype=np.uint64).astype(np.uint32) for _ in range(200)]
+    keys = [np.zeros(2, np.uint32), np.full(2, 0xFFFFFFFF, np.uint32)]
+    keys += [rng.integers(0, 2 ** 32, 2, dtype=np.uint64).astype(np.uint32) for _ in range(200)]
+    for ctr, key in zip(cases, keys):
+        ours = P.philox(ctr, key)
+        ref = np.zeros(4, np.uint32)
+        L.torch_philox(ctr.ctypes.data, key.ctypes.data, ref.ctypes.data)
+        assert np.array_equal(ours, ref), (ctr, key, ours, ref)
+
+
+def test_block_counter_layout(oracle_lib):
+    """or_block is Philox on counter (m, p, tag<<16 | j, instance), key = seed."""
+    seed = 0x0123456789ABCDEF
+    b = P.blocks(seed, 7, 2, 11, 5, 3, j=4)
+    for k in range(3):
+        ref = P.philox([11, 5 + k, (2 << 16) | 4, 7], [seed & 0xFFFFFFFF, seed >> 32])
+        assert np.array_equal(b[k], ref)
+
+
+def test_normals_distribution(oracle_lib):
+    n = 400_000
+    z = P.normals(0, 0, 0, 17, 0, n, 2)
+    for col in range(2):
+        v = z[:, col]
+        assert abs(v.mean()) < 5.0 / np.sqrt(n)
+        assert abs(v.var() - 1.0) < 5.0 * np.sqrt(2.0 / n)
+        ks = st.kstest(v, "norm").statistic
+        assert ks < 1.63 / np.sqrt(n)  # KS critical value at alpha = 1e-2
+    # the two members of a pair and neighbouring particles are uncorrelated
+    assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 5.0 / np.sqrt(n)
+    assert abs(np.corrcoef(z[:-1, 0], z[1:, 0])[0, 1]) < 5.0 / np.sqrt(n)
+
+
+def test_normal_streams_distinct(oracle_lib):
+    """Different steps, tags and instances give unrelated numbers."""
+    n = 50_000
+    a = P.normals(0, 0, 0, 3, 0, n, 1)[:, 0]
+    for other in (P.normals(0, 0, 0, 4, 0, n, 1), P.normals(0, 0, 1, 3, 0, n, 1),
+                  P.normals(0, 1, 0, 3, 0, n, 1), P.normals(1, 0, 0, 3, 0, n, 1)):
+        assert abs(np.corrcoef(a, other[:, 0])[0, 1]) < 5.0 / np.sqrt(n)
+
+
+def test_normals_extreme_uniforms_are_finite(oracle_lib):
+    """u1 lies in (0, 1], so log(u1) is finite for every block."""
+    z = P.normals(5, 3, 0, 0, 0, 200_000, 2)
+    assert np.all(np.isfinite(z))
+    assert np.abs(z).max() < 9.0  # sqrt(-2 log 2^-54) = 8.65 bounds |z|
+
+
+def test_coupling_and_instance_params(oracle_lib):
+    a = P.coupling(0, 0, 32)
+    assert a.shape == (32,) and np.all(a >= 0.5) and np.all(a < 1.5)
+    assert len(set(a.tolist())) == 32
+    seen_n, seen_k = set(), set()
+    for inst in range(256):
+        eps, lam, n, k = P.instance_params(0, inst)
+        assert 1e-3 <= eps <= 1e-1 and 0.5 <= lam <= 2.0
+        assert n in [2 ** e for e in range(12, 19)] and 8 <= k <= 64
+        seen_n.add(n)
+        seen_k.add(k)
+    assert len(seen_n) == 7 and len(seen_k) > 40
