@@ -1,0 +1,209 @@
+/*
+ * pr.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of micro-macro parareal for slow-fast SDEs (Legoll, Lelievre, Myerscough,
+ * Samaey, "Parareal computation of stochastic differential equations with
+ * time-scale separation: a numerical study", arXiv 1912.09240).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: PR_OK (0) on success, a negative pr_status otherwise;
+ *    pr_last_error() then returns a thread-local message.  Invalid arguments
+ *    are rejected before anything is launched.
+ *  - Pointers are DEVICE pointers (memory of the current HIP device) owned by
+ *    the caller unless the comment says "host".  The library never frees or
+ *    reallocates caller memory.  The only library-owned memory lives inside
+ *    the opaque handles returned by the *_create calls and is released by the
+ *    matching *_destroy call.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *    on it and return without waiting, except the *_create calls and
+ *    pr_parareal_iterate when it is asked for host error values.
+ *  - Layouts are structure-of-arrays, slice-major: x[k][n] is particle p of
+ *    slice k at x[k*n + p]; the fast variables are y[k][d][n].
+ *  - Symbols of the paper <-> names here: P particles = n, N slices =
+ *    n_slices (k when a count of slices is passed), I cells = n_cells,
+ *    delta t = dt, the levels p_j = j/Q of the quantile knots use Q = n_q.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PR_OK = 0,
+    PR_E_INVALID = -1,     /* an argument is out of range or inconsistent   */
+    PR_E_HIP = -2,         /* a HIP runtime call failed (message says which) */
+    PR_E_NOMEM = -3,       /* workspace too small or device allocation failed */
+    PR_E_UNSUPPORTED = -4  /* valid request that this build does not serve  */
+} pr_status;
+
+/* Precision of the particle state and of the Euler-Maruyama arithmetic.
+ * Moments, knots, coarse model and matching offsets are always FP64. */
+enum { PR_F64 = 64, PR_F32 = 32 };
+
+/* Flags of pr_parareal_create. */
+enum {
+    PR_REUSE_COARSE = 1,   /* q_c^* = C(q_k^n) instead of C(R(X_k^n))          */
+    PR_SKIP_CONVERGED = 2  /* do not re-run the fine propagator on slices whose
+                              start is already exact (n < k, Sec. 3.3.3)       */
+};
+
+/*
+ * Slow-fast SDE (Sec. 2.1.1, eq. (SDEx)/(SDEy)) with tau_x = 1, D = E = 1/beta,
+ * slow potential F = c3 x^4/4 + c1 x^2/2 + lambda (x - mean_i y_i)^2/2 and
+ * fast potential G = sum_i (y_i - a_i x)^2/2:
+ *   dX   = -(c3 X^3 + c1 X + lambda (X - mean_i Y_i)) dt + sqrt(2/beta) dW_0
+ *   dY_i = -(1/eps) (Y_i - a_i X) dt + sqrt(2/(beta eps)) dW_{i+1}
+ */
+typedef struct pr_sde {
+    int d_fast;        /* d >= 1; this build serves d in {1, 2, 3, 4, 8, 16, 32} */
+    int precision;     /* PR_F64 or PR_F32                                     */
+    double lambda;     /* coupling                                             */
+    double eps;        /* time-scale separation, > 0                           */
+    double beta;       /* inverse temperature, > 0                             */
+    double c3, c1;     /* slow potential coefficients                          */
+    const double *a;   /* device, d_fast coefficients a_i; NULL means all 1    */
+} pr_sde;
+
+/* Time slices (Sec. 3.1): S fine steps of dt split into n_slices slices;
+ * slice n covers the global steps [floor(n S/N), floor((n+1) S/N)). */
+typedef struct pr_schedule {
+    int64_t total_steps;  /* S >= n_slices                                    */
+    int n_slices;         /* N >= 1                                           */
+    double dt;            /* fine step, > 0                                   */
+} pr_schedule;
+
+/* Coarse grid (Sec. 2.2.2): n_cells uniform cells on [x_lo, x_hi]; quantile
+ * knots at p_j = j/n_q, j = 0..n_q (Sec. 4.4). */
+typedef struct pr_grid {
+    int n_cells;          /* I >= 3                                           */
+    double x_lo, x_hi;    /* x_lo < x_hi                                      */
+    int n_q;              /* Q >= 2                                           */
+} pr_grid;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *pr_last_error(void);
+
+/* Library ABI version (incremented on incompatible changes). */
+int pr_version(void);
+
+/*
+ * Noise.  Every normal number comes from Philox4x32-10 (Salmon et al., SC'11)
+ * with key (lo32(seed), hi32(seed)) and counter (m, p, tag<<16 | j, instance),
+ * m the global step, p the particle, j the pair index; the two 53-bit uniforms
+ * of a block give two normals by Box-Muller; normal 2j and 2j+1 of a particle
+ * use pair j.  Tags: 0 EM increments, 1 initial ensemble, 2 coefficients a_i,
+ * 3 batched-instance parameters.  Noise therefore depends only on
+ * (seed, instance, step, particle): a slice run twice uses the same numbers
+ * (Sec. 6) and any subset of particles can be recomputed.
+ */
+
+/* a[i] = 0.5 + u (u uniform of block (tag 2, m = 0, p = i)), i < d.
+ * a: device, d doubles. */
+int pr_draw_coupling(uint64_t seed, uint32_t instance, int d, double *a, void *stream);
+
+/* Initial ensemble: X0 = N(0, 1/4) (normal 0), Y0_i = a_i X0 + beta^-1/2 z
+ * (normal i+1), tag 1, m = 0.  x: [n], y: [d][n], precision of sde. */
+int pr_init_ensemble(const pr_sde *sde, uint64_t seed, uint32_t instance, int64_t n,
+                     void *x, void *y, void *stream);
+
+/*
+ * Fine propagator F (Sec. 3.2.1): Euler-Maruyama, eq. (EMx)/(EMy), drift at
+ * the old state, over every slice in [slice_first, slice_first+slice_count)
+ * at once.  x: [slice_count][n], y: [slice_count][d][n], in place: on entry
+ * the state at the start of each slice, on exit at its end.  Each particle
+ * keeps its state in registers; normals are generated in the kernel.
+ */
+int pr_fine_propagate(const pr_sde *sde, const pr_schedule *sched, uint64_t seed,
+                      uint32_t instance, int64_t n, int slice_first, int slice_count,
+                      void *x, void *y, void *stream);
+
+/*
+ * Restriction R (Sec. 3.2.2) of k ensembles of n particles to the empirical
+ * quantile function of the slow variable (Sec. 4.4).  x: [k][n] (FP64, or
+ * FP32 when precision == PR_F32), read only.  Outputs (any may be NULL
+ * except q):
+ *   q        [k][n_q+1]  knots at p_j = j/Q, midpoint (Hazen) convention:
+ *                        t = p_j n - 1/2, min at t <= 0, max at t >= n-1,
+ *                        else linear between order statistics floor(t), +1;
+ *   rank     [k][n]      position of particle p in the stable ascending
+ *                        order by (value, p); -0.0 orders before +0.0;
+ *   perm     [k][n]      particle at each position (inverse of rank);
+ *   x_sorted [k][n]      values in that order (FP64);
+ *   moments  [k][4]      (1/n) sum_p x_p^m, m = 1..4 (eq. (MCestimator));
+ *   hist     [k][I]      counts in cells floor((x-x_lo) I/(x_hi-x_lo))
+ *                        clamped to [0, I-1] (eq. (binning)); uses the
+ *                        cells of hist_grid (n_q of hist_grid is ignored).
+ * hist_grid may be NULL when hist is NULL.  n_q >= 1.
+ * ws: device workspace of at least pr_restrict_workspace_size() bytes.
+ */
+size_t pr_restrict_workspace_size(int64_t n, int k, int precision);
+int pr_restrict_quantiles(const void *x, int precision, int64_t n, int k, int n_q,
+                          const pr_grid *hist_grid, double *q, uint32_t *rank, uint32_t *perm,
+                          double *x_sorted, double *moments, uint32_t *hist,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Matching preserving the fast marginal (Sec. 5.1, eq. (transformation)) in
+ * quantile add/subtract form: for every particle of each of the k ensembles,
+ *   u = (rank + 1/2)/n, j = min(floor(u Q), Q-1), w = u Q - j,
+ *   x_out = x_prior + (1-w) d_j + w d_{j+1},  d = q_target - q_prior.
+ * The fast variables and weights are untouched.  With q_target == q_prior the
+ * output equals the input bitwise (eq. (projection)).  x_out may alias
+ * x_prior.  q_*: [k][n_q+1]; rank: [k][n] from pr_restrict_quantiles of
+ * x_prior; x_*: [k][n] of the given precision.
+ */
+int pr_match_quantiles(const double *q_target, const double *q_prior, const uint32_t *rank,
+                       int64_t n, int k, int n_q, const void *x_prior, void *x_out,
+                       int precision, void *stream);
+
+/*
+ * Coarse propagator C (Sec. 2.2): finite volumes for the slow Fokker-Planck
+ * equation eq. (FPz) with the effective drift of eq. (Fbar),
+ * V' = c3 x^3 + (c1 + lambda (1 - mean a)) x, Dbar = 1/beta, zero flux at the
+ * grid ends, advanced by the exact exponential E(tau) = exp(A tau) with tau
+ * the slice length (Sec. 2.2.2).  pr_coarse_create builds A on the host and
+ * E(tau) on the device for every distinct slice length (synchronous).
+ * pr_coarse_fp_step maps knots -> cell masses (piecewise-linear cdf through
+ * the knots, eq. (discr_cdf)) -> E masses, clipped at 0 -> knots (flat
+ * stretches give their midpoint, end knots are the grid ends), for slices
+ * [slice_first, slice_first+slice_count) in parallel.  q_in, q_out:
+ * [count][n_q+1]; rho_out: [count][I] or NULL.
+ */
+int pr_coarse_create(const pr_sde *sde, const pr_schedule *sched, const pr_grid *grid,
+                     void *stream, void **coarse);
+int pr_coarse_fp_step(const void *coarse, int slice_first, int slice_count,
+                      const double *q_in, double *q_out, double *rho_out, void *stream);
+/* Device pointer to E of slice n ([I][I], row-major) for inspection. */
+int pr_coarse_matrix(const void *coarse, int slice, const double **E);
+int pr_coarse_destroy(void *coarse);
+
+/*
+ * Micro-macro parareal (Sec. 3.2.3-3.2.4) with the quantile iterator
+ * (Sec. 4.4, eq. (quantile_reconstruction); PAVA monotone repair) and
+ * fast-marginal matching.  pr_parareal_create draws the initial ensemble and
+ * runs the zeroth iteration (coarse pass from R(X0), matching against X0);
+ * it owns all state buffers.  pr_parareal_iterate runs n_iter iterations
+ * k -> k+1: fine propagation of every slice, restriction, coarse correction,
+ * serial J chain, matching.  If q_ref (device, [N+1][n_q+1], the knots of the
+ * serial fine run) is given, err_out (host, [n_iter][2]) receives for each
+ * iteration the RMS knot error at n = N and its maximum over n.
+ * pr_parareal_state copies the state at time index t (0..N) out: x [n],
+ * y [d][n], q [n_q+1] (knots of that state), any may be NULL.
+ */
+int pr_parareal_create(const pr_sde *sde, const pr_schedule *sched, const pr_grid *grid,
+                       uint64_t seed, uint32_t instance, int64_t n, int flags, void *stream,
+                       void **h);
+int pr_parareal_iterate(void *h, int n_iter, const double *q_ref, double *err_out, void *stream);
+int pr_parareal_state(void *h, int t, void *x, void *y, double *q, void *stream);
+int pr_parareal_iteration(const void *h);
+int pr_parareal_destroy(void *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H */

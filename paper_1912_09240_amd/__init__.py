@@ -1,0 +1,240 @@
+"""Python binding of the MI355X micro-macro parareal library (``libpr.so``).
+
+Argument marshalling only: every function forwards to the C entry point of the
+same name in ``include/pr.h``; all computation happens in the HIP kernels of
+the library.  Tensors are passed by device pointer, streams as the raw
+hipStream_t of ``torch.cuda`` (the current stream when none is given).
+Importing this module does not need a GPU; calling into the library does, and
+a missing library is an error, never a fallback.
+"""
+import ctypes
+import os
+
+__all__ = [
+    "Sde", "Schedule", "Grid", "PrError", "lib", "available",
+    "pr_version", "pr_last_error", "pr_draw_coupling", "pr_init_ensemble", "pr_fine_propagate",
+    "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles",
+    "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy",
+    "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
+    "pr_parareal_destroy", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpr.so")
+
+PR_F64, PR_F32 = 64, 32
+PR_REUSE_COARSE, PR_SKIP_CONVERGED = 1, 2
+
+_c_int, _c_i64, _c_u32, _c_u64, _c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class _CSde(ctypes.Structure):
+    _fields_ = [("d_fast", _c_int), ("precision", _c_int), ("lambda_", _c_dbl), ("eps", _c_dbl),
+                ("beta", _c_dbl), ("c3", _c_dbl), ("c1", _c_dbl), ("a", _vp)]
+
+
+class _CSchedule(ctypes.Structure):
+    _fields_ = [("total_steps", _c_i64), ("n_slices", _c_int), ("dt", _c_dbl)]
+
+
+class _CGrid(ctypes.Structure):
+    _fields_ = [("n_cells", _c_int), ("x_lo", _c_dbl), ("x_hi", _c_dbl), ("n_q", _c_int)]
+
+
+class Sde:
+    """Slow-fast SDE parameters (pr_sde).  ``a`` is a device tensor of d
+    doubles or None (all ones)."""
+
+    def __init__(self, lam=1.0, eps=0.1, beta=2.0, c3=1.0, c1=-1.0, d=1, precision=PR_F64, a=None):
+        self.lam, self.eps, self.beta, self.c3, self.c1 = lam, eps, beta, c3, c1
+        self.d, self.precision, self.a = d, precision, a
+
+    def c(self):
+        return _CSde(self.d, self.precision, self.lam, self.eps, self.beta, self.c3, self.c1,
+                     _ptr(self.a) if self.a is not None else None)
+
+
+class Schedule:
+    """pr_schedule: S fine steps of dt in n_slices slices."""
+
+    def __init__(self, total_steps, n_slices, dt):
+        self.total_steps, self.n_slices, self.dt = int(total_steps), int(n_slices), float(dt)
+
+    def c(self):
+        return _CSchedule(self.total_steps, self.n_slices, self.dt)
+
+
+class Grid:
+    """pr_grid: n_cells on [x_lo, x_hi], knots at j/n_q."""
+
+    def __init__(self, n_cells=200, x_lo=-3.0, x_hi=3.0, n_q=100):
+        self.n_cells, self.x_lo, self.x_hi, self.n_q = int(n_cells), float(x_lo), float(x_hi), int(n_q)
+
+    def c(self):
+        return _CGrid(self.n_cells, self.x_lo, self.x_hi, self.n_q)
+
+
+class PrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pr status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+_SIGS = {
+    "pr_last_error": (ctypes.c_char_p, []),
+    "pr_version": (_c_int, []),
+    "pr_draw_coupling": (_c_int, [_c_u64, _c_u32, _c_int, _vp, _vp]),
+    "pr_init_ensemble": (_c_int, [ctypes.POINTER(_CSde), _c_u64, _c_u32, _c_i64, _vp, _vp, _vp]),
+    "pr_fine_propagate": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64,
+                                   _c_int, _c_int, _vp, _vp, _vp]),
+    "pr_restrict_workspace_size": (ctypes.c_size_t, [_c_i64, _c_int, _c_int]),
+    "pr_restrict_quantiles": (_c_int, [_vp, _c_int, _c_i64, _c_int, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, _vp,
+                                       _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_match_quantiles": (_c_int, [_vp, _vp, _vp, _c_i64, _c_int, _c_int, _vp, _vp, _c_int, _vp]),
+    "pr_coarse_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid), _vp,
+                                  ctypes.POINTER(_vp)]),
+    "pr_coarse_fp_step": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
+    "pr_coarse_matrix": (_c_int, [_vp, _c_int, ctypes.POINTER(_vp)]),
+    "pr_coarse_destroy": (_c_int, [_vp]),
+    "pr_parareal_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid),
+                                    _c_u64, _c_u32, _c_i64, _c_int, _vp, ctypes.POINTER(_vp)]),
+    "pr_parareal_iterate": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "pr_parareal_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp]),
+    "pr_parareal_iteration": (_c_int, [_vp]),
+    "pr_parareal_destroy": (_c_int, [_vp]),
+}
+
+
+def available():
+    return os.path.exists(LIB_PATH)
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built: run paper_1912_09240_amd/build.py (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status):
+    if status != 0:
+        raise PrError(status, lib().pr_last_error().decode())
+
+
+def pr_version():
+    return lib().pr_version()
+
+
+def pr_last_error():
+    return lib().pr_last_error().decode()
+
+
+def pr_draw_coupling(seed, instance, d, a, stream=None):
+    _check(lib().pr_draw_coupling(seed, instance, d, _ptr(a), _stream(stream)))
+
+
+def pr_init_ensemble(sde, seed, instance, n, x, y, stream=None):
+    s = sde.c()
+    _check(lib().pr_init_ensemble(ctypes.byref(s), seed, instance, n, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def pr_fine_propagate(sde, sched, seed, instance, n, slice_first, slice_count, x, y, stream=None):
+    s, c = sde.c(), sched.c()
+    _check(lib().pr_fine_propagate(ctypes.byref(s), ctypes.byref(c), seed, instance, n, slice_first, slice_count,
+                                   _ptr(x), _ptr(y), _stream(stream)))
+
+
+def pr_restrict_workspace_size(n, k, precision=PR_F64):
+    return lib().pr_restrict_workspace_size(n, k, precision)
+
+
+def pr_restrict_quantiles(x, precision, n, k, n_q, q, ws, rank=None, perm=None, x_sorted=None, moments=None,
+                          hist=None, hist_grid=None, stream=None):
+    g = ctypes.byref(hist_grid.c()) if hist_grid is not None else None
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().pr_restrict_quantiles(_ptr(x), precision, n, k, n_q, g, _ptr(q), _ptr(rank), _ptr(perm),
+                                       _ptr(x_sorted), _ptr(moments), _ptr(hist), _ptr(ws), nbytes, _stream(stream)))
+
+
+def pr_match_quantiles(q_target, q_prior, rank, n, k, n_q, x_prior, x_out, precision=PR_F64, stream=None):
+    _check(lib().pr_match_quantiles(_ptr(q_target), _ptr(q_prior), _ptr(rank), n, k, n_q, _ptr(x_prior),
+                                    _ptr(x_out), precision, _stream(stream)))
+
+
+def pr_coarse_create(sde, sched, grid, stream=None):
+    h = _vp()
+    s, c, g = sde.c(), sched.c(), grid.c()
+    _check(lib().pr_coarse_create(ctypes.byref(s), ctypes.byref(c), ctypes.byref(g), _stream(stream),
+                                  ctypes.byref(h)))
+    return h
+
+
+def pr_coarse_fp_step(h, slice_first, slice_count, q_in, q_out, rho_out=None, stream=None):
+    _check(lib().pr_coarse_fp_step(h, slice_first, slice_count, _ptr(q_in), _ptr(q_out), _ptr(rho_out),
+                                   _stream(stream)))
+
+
+def pr_coarse_matrix(h, slice_index):
+    p = _vp()
+    _check(lib().pr_coarse_matrix(h, slice_index, ctypes.byref(p)))
+    return p.value
+
+
+def pr_coarse_destroy(h):
+    _check(lib().pr_coarse_destroy(h))
+
+
+def pr_parareal_create(sde, sched, grid, seed, instance, n, flags=0, stream=None):
+    h = _vp()
+    s, c, g = sde.c(), sched.c(), grid.c()
+    _check(lib().pr_parareal_create(ctypes.byref(s), ctypes.byref(c), ctypes.byref(g), seed, instance, n, flags,
+                                    _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_iterate(h, n_iter, q_ref=None, err_out=None, stream=None):
+    """err_out: a host buffer (e.g. a numpy float64 array of 2*n_iter) or None."""
+    ep = None
+    if err_out is not None:
+        ep = err_out.ctypes.data_as(_vp) if hasattr(err_out, "ctypes") else _ptr(err_out)
+    _check(lib().pr_parareal_iterate(h, n_iter, _ptr(q_ref), ep, _stream(stream)))
+
+
+def pr_parareal_state(h, t, x=None, y=None, q=None, stream=None):
+    _check(lib().pr_parareal_state(h, t, _ptr(x), _ptr(y), _ptr(q), _stream(stream)))
+
+
+def pr_parareal_iteration(h):
+    return lib().pr_parareal_iteration(h)
+
+
+def pr_parareal_destroy(h):
+    _check(lib().pr_parareal_destroy(h))

@@ -1,0 +1,199 @@
+// Internal helpers of the HIP library: error reporting, launch checks and the
+// device-side counter-based noise (Philox4x32-10 + Box-Muller).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "pr.h"
+
+namespace pr {
+
+// ---------------------------------------------------------------------------
+// Errors: every entry point returns a pr_status; the message is thread-local.
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define PR_REQUIRE(cond, ...)                                   \
+    do {                                                        \
+        if (!(cond)) {                                          \
+            ::pr::set_error(__VA_ARGS__);                       \
+            return PR_E_INVALID;                                \
+        }                                                       \
+    } while (0)
+
+#define PR_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::pr::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                            __FILE__, __LINE__);                                     \
+            return PR_E_HIP;                                                         \
+        }                                                                            \
+    } while (0)
+
+#define PR_LAUNCHED()                                                                \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess) {                                                      \
+            ::pr::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                     \
+            return PR_E_HIP;                                                         \
+        }                                                                            \
+    } while (0)
+
+#define PR_CHECK(expr)               \
+    do {                             \
+        int s_ = (expr);             \
+        if (s_ != PR_OK) return s_;  \
+    } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool valid_precision(int p) { return p == PR_F64 || p == PR_F32; }
+inline bool valid_d(int d) { return d == 1 || d == 2 || d == 3 || d == 4 || d == 8 || d == 16 || d == 32; }
+
+int check_sde(const pr_sde *s);
+int check_schedule(const pr_schedule *s);
+int check_grid(const pr_grid *g);
+
+// First step of slice n: floor(n S / N), computed without overflow for
+// S < 2^63 / N.
+__host__ __device__ inline int64_t slice_begin(int64_t S, int N, int n) {
+    return (int64_t)((__int128)n * S / N);
+}
+
+// ---------------------------------------------------------------------------
+// Noise.  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+// with the key advanced by the Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct Block {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block{c0, c1, c2, c3};
+}
+
+struct Key {
+    uint32_t k0, k1;
+};
+inline Key make_key(uint64_t seed) { return Key{(uint32_t)seed, (uint32_t)(seed >> 32)}; }
+
+__device__ __forceinline__ Block noise_block(Key key, uint32_t inst, uint32_t tag, uint32_t m,
+                                             uint32_t p, uint32_t j) {
+    return philox(m, p, (tag << 16) | j, inst, key.k0, key.k1);
+}
+
+// 53-bit uniforms: u1 in (0, 1] (never 0, so log is finite), u2 in [0, 1).
+__device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u2) {
+    const double a = (double)(b.w0 >> 5) * 67108864.0 + (double)(b.w1 >> 6);
+    const double c = (double)(b.w2 >> 5) * 67108864.0 + (double)(b.w3 >> 6);
+    u1 = (a + 0.5) * 0x1p-53;
+    u2 = c * 0x1p-53;
+}
+
+// Box-Muller: z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 log u1).
+// The angle goes through sincospi, so no range reduction by 2 pi is needed.
+__device__ __forceinline__ void box_muller(const Block &b, double &z0, double &z1) {
+    double u1, u2;
+    uniforms53(b, u1, u2);
+    const double r = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// FP32 variant: 24-bit uniforms u1 in (0, 1], u2 in [0, 1).
+__device__ __forceinline__ void box_muller_f32(const Block &b, float &z0, float &z1) {
+    const float u1 = ((float)(b.w0 >> 8) + 0.5f) * 0x1p-24f;
+    const float u2 = (float)(b.w2 >> 8) * 0x1p-24f;
+    const float r = sqrtf(-2.0f * logf(u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+// Orderable 64-bit key of a double: unsigned order == numeric order,
+// -0.0 before +0.0.
+__device__ __forceinline__ uint64_t key_of(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint64_t mask = (uint64_t)((int64_t)b >> 63) | 0x8000000000000000ull;
+    return b ^ mask;
+}
+__device__ __forceinline__ double value_of(uint64_t k) {
+    const uint64_t b = (k & 0x8000000000000000ull) ? (k ^ 0x8000000000000000ull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ uint32_t key_of(float x) {
+    const uint32_t b = (uint32_t)__float_as_uint(x);
+    const uint32_t mask = (uint32_t)((int32_t)b >> 31) | 0x80000000u;
+    return b ^ mask;
+}
+__device__ __forceinline__ double value_of(uint32_t k) {
+    const uint32_t b = (k & 0x80000000u) ? (k ^ 0x80000000u) : ~k;
+    return (double)__uint_as_float(b);
+}
+
+// ---------------------------------------------------------------------------
+// Internal entry points shared between translation units (no validation).
+// ---------------------------------------------------------------------------
+// Per-segment strides (in elements) let one prior serve several targets
+// (stride 0), as in the zeroth iteration where every slice is matched
+// against the initial ensemble.
+struct MatchArgs {
+    const double *qt;
+    int64_t qt_stride;
+    const double *qp;
+    int64_t qp_stride;
+    const uint32_t *rank;
+    int64_t rank_stride;
+    const void *xin;
+    int64_t xin_stride;
+    void *xout;
+    int64_t xout_stride;
+};
+int match_strided(const MatchArgs &a, int64_t n, int k, int nq, int precision, hipStream_t st);
+
+// x_in/y_in and x_out/y_out may alias (in place).
+int fine_propagate(const pr_sde *sde, const pr_schedule *sch, uint64_t seed, uint32_t inst, int64_t n,
+                   int slice_first, int slice_count, const void *x_in, const void *y_in, void *x_out,
+                   void *y_out, hipStream_t st);
+int init_ensemble(const pr_sde *sde, uint64_t seed, uint32_t inst, int64_t n, void *x, void *y, hipStream_t st);
+
+size_t restrict_ws(int64_t n, int k, int precision);
+int restrict_quantiles(const void *x, int precision, int64_t n, int k, int nq, const pr_grid *hg, double *q,
+                       uint32_t *rank, uint32_t *perm, double *xs, double *mom, uint32_t *hist, void *ws,
+                       hipStream_t st);
+
+struct Coarse;
+int coarse_create(const pr_sde *sde, const pr_schedule *sch, const pr_grid *grid, hipStream_t st, Coarse **out);
+int coarse_step(const Coarse *c, int first, int count, const double *q_in, int in_stride, double *q_out,
+                int out_stride, double *rho_out, hipStream_t st);
+int coarse_jump(const Coarse *c, int n, const double *q_cur, const double *qf, const double *qcs, double *q_next,
+                double *qc_out, hipStream_t st);
+void coarse_free(Coarse *c);
+
+}  // namespace pr

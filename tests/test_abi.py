@@ -1,0 +1,87 @@
+"""The C-ABI library builds, loads and exports every entry point declared in
+include/pr.h; argument validation rejects bad calls before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1912_09240_amd as pr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "pr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not pr.available():
+        from paper_1912_09240_amd import build
+        build.build()
+    return pr.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in pr.__all__, n
+
+
+def test_version_and_error_string(lib):
+    assert pr.pr_version() == 1
+    assert isinstance(pr.pr_last_error(), str)
+
+
+def test_workspace_size_is_monotone(lib):
+    a = pr.pr_restrict_workspace_size(1000, 3)
+    b = pr.pr_restrict_workspace_size(100000, 3)
+    c = pr.pr_restrict_workspace_size(100000, 3, pr.PR_F32)
+    assert 0 < a < b and c < b
+    # keys (2 x 8 B) + payload (2 x 4 B) per element at least
+    assert b >= 100000 * 3 * 24
+
+
+def test_validation_rejects_before_launch(lib):
+    L = lib
+    # NULL sde
+    assert L.pr_init_ensemble(None, 0, 0, 10, None, None, None) == -1
+    assert "sde" in pr.pr_last_error()
+    # bad precision / d
+    bad = pr.Sde(d=5).c()
+    assert L.pr_init_ensemble(ctypes.byref(bad), 0, 0, 10, None, None, None) == -1
+    bad = pr.Sde(precision=16).c()
+    assert L.pr_init_ensemble(ctypes.byref(bad), 0, 0, 10, None, None, None) == -1
+    # negative eps
+    bad = pr.Sde(eps=-1.0).c()
+    assert L.pr_init_ensemble(ctypes.byref(bad), 0, 0, 10, None, None, None) == -1
+    # slices outside the schedule
+    s, c = pr.Sde().c(), pr.Schedule(100, 4, 1e-3).c()
+    assert L.pr_fine_propagate(ctypes.byref(s), ctypes.byref(c), 0, 0, 10, 3, 2, None, None, None) == -1
+    # schedule with fewer steps than slices
+    c2 = pr.Schedule(3, 4, 1e-3).c()
+    assert L.pr_fine_propagate(ctypes.byref(s), ctypes.byref(c2), 0, 0, 10, 0, 1, None, None, None) == -1
+    # workspace too small
+    assert L.pr_restrict_quantiles(ctypes.c_void_p(16), 64, 1000, 2, 100, None, ctypes.c_void_p(16), None, None,
+                                   None, None, None, ctypes.c_void_p(16), 10, None) == -3
+    # grid checks
+    g = pr.Grid(n_cells=2).c()
+    h = ctypes.c_void_p()
+    assert L.pr_coarse_create(ctypes.byref(s), ctypes.byref(pr.Schedule(100, 4, 1e-3).c()), ctypes.byref(g), None,
+                              ctypes.byref(h)) == -1
+    g = pr.Grid(x_lo=1.0, x_hi=0.0).c()
+    assert L.pr_parareal_create(ctypes.byref(s), ctypes.byref(pr.Schedule(100, 4, 1e-3).c()), ctypes.byref(g), 0,
+                                0, 10, 0, None, ctypes.byref(h)) == -1
+    # unknown flags
+    g = pr.Grid().c()
+    assert L.pr_parareal_create(ctypes.byref(s), ctypes.byref(pr.Schedule(100, 4, 1e-3).c()), ctypes.byref(g), 0,
+                                0, 10, 64, None, ctypes.byref(h)) == -1
+    # matching without pointers
+    assert L.pr_match_quantiles(None, None, None, 10, 1, 100, None, None, 64, None) == -1
+    # iterate on a NULL handle
+    assert L.pr_parareal_iterate(None, 1, None, None, None) == -1
