@@ -1,0 +1,174 @@
+"""Benchmark of the micro-macro parareal hot path on one MI355X.
+
+Workload (the large configuration of the method): the 2-D slow-fast SDE
+dX = -(X^3 - X + lambda (X - Y)) dt + sqrt(2/beta) dW1,
+dY = -(1/eps)(Y - X) dt + sqrt(2/(beta eps)) dW2, lambda = 1, beta = 2,
+eps = 0.01; P = 2^20 FP64 particles, dt = 1e-4, T = 10 (S = 1e5 steps) in
+N = 64 slices, coarse grid of 1024 cells on [-3, 3], 100 quantile levels.
+Synthetic, Philox-seeded inputs (seed 0).
+
+A step is one parareal iteration k -> k+1 over the whole hot path: fine
+propagation of all 64 slices in one launch, restriction (sort, ranks,
+knots) of the fine results, coarse propagation of every slice, the serial
+quantile-iterator chain, matching of every slice, and the knots of the new
+states with their RMS error to the serial fine run.  value = P * S / (time
+of one step): fine particle-steps per second of the whole iteration.
+
+The roofline object is for the dominant kernel (the fine propagator): its
+duration is the summed HIP-event time of its launches over the timed steps,
+recorded on the stream it runs on.  The CPU baseline is the plain oracle
+running one iteration of the same workload on a bounded particle sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (fwd+adjoint) and parareal sweep time vs plain, same tol"
+WORKLOAD = dict(lam=1.0, beta=2.0, eps=0.01, n=2 ** 20, dt=1e-4, T=10.0, K=64, cells=1024, nq=100, seed=0)
+
+# Minimal VALU instructions per FP64 particle-step (d = 1), counted from the
+# operations the method must perform on gfx950: Philox4x32-10 with the
+# particle index as the only lane-varying counter word (16 lane-varying
+# 32x32->64 products + 18 xor), two 53-bit uniforms (10), ln u1 to FP64
+# accuracy (25), sqrt (9), sin/cos of 2 pi u2 by quadrant reduction (24), the
+# two Box-Muller products (2) and the Euler-Maruyama update (9): 113.  The
+# derivation is in the design notes; the figure is frozen so that the
+# fraction moves only with the kernel's speed.
+VALU_OPS_PER_STEP = 113
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
+VALU_PEAK = 256 * 64 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=8192, help="particles in the oracle's sample")
+    ap.add_argument("--flags", type=int, default=0, help="parareal flags (1 reuse coarse, 2 skip converged)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_sample):
+    """One parareal iteration of the workload by the oracle, on particles
+    0..n_sample-1 (counter-based noise makes the sample exact)."""
+    from oracle import coarse as OC
+    from oracle import iterate as OI
+    from oracle import particles as OP
+    w = WORKLOAD
+    sde = OP.Sde(lam=w["lam"], eps=w["eps"], beta=w["beta"])
+    po, hp = OI.micmac_parareal(sde, w["seed"], 0, n_sample, w["T"], w["dt"], w["K"], OC.Grid(w["cells"]), w["nq"])
+    t0 = time.perf_counter()
+    po.iterate()
+    t = time.perf_counter() - t0
+    S = hp["S"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n_sample * S / t, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"one parareal iteration (fine propagation of all {w['K']} slices, restriction, coarse "
+                       f"propagation, quantile-iterator chain, matching) of the large workload on particles "
+                       f"0..{n_sample - 1}; {t:.2f} s on {threads} OpenMP threads")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding of the slices is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1912_09240_amd as pr
+
+    w = WORKLOAD
+    S = int(round(w["T"] / w["dt"]))
+    dt = w["T"] / S
+    n, K, nq = w["n"], w["K"], w["nq"]
+    sde = pr.Sde(lam=w["lam"], eps=w["eps"], beta=w["beta"])
+    sched = pr.Schedule(S, K, dt)
+    grid = pr.Grid(n_cells=w["cells"], n_q=nq)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    # serial fine run: reference knots q_ref[t] for the error metric
+    log("serial fine reference")
+    t0 = time.perf_counter()
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, w["seed"], 0, n, x, y)
+    qref = torch.empty((K + 1, nq + 1), dtype=torch.float64, device="cuda")
+    ws = torch.empty(pr.pr_restrict_workspace_size(n, 1), dtype=torch.uint8, device="cuda")
+    pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, nq, qref[0], ws)
+    for s in range(K):
+        pr.pr_fine_propagate(sde, sched, w["seed"], 0, n, s, 1, x, y)
+        pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, nq, qref[s + 1], ws)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    del ws, x, y
+
+    log("parareal create (zeroth iteration)")
+    t0 = time.perf_counter()
+    h = pr.pr_parareal_create(sde, sched, grid, w["seed"], 0, n, args.flags | pr.PR_PROFILE)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    errs = np.zeros(2 * (args.warmup + args.steps))
+    try:
+        for i in range(args.warmup):
+            pr.pr_parareal_iterate(h, 1, q_ref=qref, err_out=errs[2 * i:])
+            log(f"warmup iteration {i + 1} done")
+        prof0, it0 = pr.pr_parareal_profile(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            j = args.warmup + i
+            pr.pr_parareal_iterate(h, 1, q_ref=qref, err_out=errs[2 * j:])
+            log(f"timed iteration {i + 1} done")
+        torch.cuda.synchronize()
+        t_steps = time.perf_counter() - t0
+        prof1, it1 = pr.pr_parareal_profile(h)
+    finally:
+        pr.pr_parareal_destroy(h)
+    phases = {k: (prof1[k] - prof0[k]) / max(1, it1 - it0) for k in prof1}
+    ms_step = 1e3 * t_steps / args.steps
+    value = n * S / (t_steps / args.steps)
+
+    fine_s = phases["fine"] / 1e3
+    fine_rate = n * S / fine_s
+    achieved = VALU_OPS_PER_STEP * fine_rate
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="Tops/s",
+                    frac=achieved / VALU_PEAK, traffic=None,
+                    kernel="fine_kernel<1,double,2> (all 64 slices, one launch)",
+                    fine_ms=phases["fine"], fine_particle_steps_per_s=fine_rate,
+                    ops_per_particle_step=VALU_OPS_PER_STEP)
+
+    out = dict(metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="slow-fast SDE, eps=0.01, P=2^20 FP64 particles, dt=1e-4, T=10 "
+                                    "(1e5 steps), 64 slices, 1024-cell coarse grid, 100 quantile levels, "
+                                    "one parareal iteration per step", particles=n, fine_steps=S, slices=K,
+                           cells=w["cells"], quantile_levels=nq, flags=args.flags, seed=w["seed"]),
+               roofline=roofline,
+               phases_ms=phases,
+               quantile_error=dict(at_T=[float(errs[2 * i]) for i in range(args.warmup + args.steps)],
+                                   max_over_slices=[float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]),
+               serial_fine_s=t_serial, create_s=t_create)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

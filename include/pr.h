@@ -47,8 +47,21 @@ enum { PR_F64 = 64, PR_F32 = 32 };
 /* Flags of pr_parareal_create. */
 enum {
     PR_REUSE_COARSE = 1,   /* q_c^* = C(q_k^n) instead of C(R(X_k^n))          */
-    PR_SKIP_CONVERGED = 2  /* do not re-run the fine propagator on slices whose
+    PR_SKIP_CONVERGED = 2, /* do not re-run the fine propagator on slices whose
                               start is already exact (n < k, Sec. 3.3.3)       */
+    PR_PROFILE = 4         /* record HIP events around each phase of an
+                              iteration (see pr_parareal_profile)              */
+};
+
+/* Phases reported by pr_parareal_profile. */
+enum {
+    PR_PH_FINE = 0,        /* fine propagator, all slices: one kernel launch   */
+    PR_PH_RESTRICT_FINE,   /* restriction of the fine results (full sort)      */
+    PR_PH_COARSE,          /* coarse propagation of all slices in parallel     */
+    PR_PH_CHAIN,           /* serial quantile-iterator chain                   */
+    PR_PH_MATCH,           /* matching of all slices                           */
+    PR_PH_RESTRICT_NEW,    /* knots of the new states (+ error)                */
+    PR_PH_COUNT
 };
 
 /*
@@ -200,6 +213,12 @@ int pr_parareal_create(const pr_sde *sde, const pr_schedule *sched, const pr_gri
 int pr_parareal_iterate(void *h, int n_iter, const double *q_ref, double *err_out, void *stream);
 int pr_parareal_state(void *h, int t, void *x, void *y, double *q, void *stream);
 int pr_parareal_iteration(const void *h);
+/* With PR_PROFILE: ms_out (host, PR_PH_COUNT doubles) receives the summed
+ * device time of each phase over all iterations since creation, measured by
+ * HIP events recorded on the iteration's stream; iterations (host, may be
+ * NULL) receives how many iterations were timed.  Without PR_PROFILE the call
+ * fails with PR_E_INVALID. */
+int pr_parareal_profile(const void *h, double *ms_out, int *iterations);
 int pr_parareal_destroy(void *h);
 
 #ifdef __cplusplus

@@ -16,14 +16,16 @@ __all__ = [
     "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles",
     "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy",
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
-    "pr_parareal_destroy", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
+    "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
+    "PR_PROFILE", "PHASES",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_F64, PR_F32 = 64, 32
-PR_REUSE_COARSE, PR_SKIP_CONVERGED = 1, 2
+PR_REUSE_COARSE, PR_SKIP_CONVERGED, PR_PROFILE = 1, 2, 4
+PHASES = ("fine", "restrict_fine", "coarse", "chain", "match", "restrict_new")
 
 _c_int, _c_i64, _c_u32, _c_u64, _c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 _vp = ctypes.c_void_p
@@ -105,6 +107,7 @@ _SIGS = {
     "pr_parareal_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp]),
     "pr_parareal_iteration": (_c_int, [_vp]),
     "pr_parareal_destroy": (_c_int, [_vp]),
+    "pr_parareal_profile": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_int)]),
 }
 
 
@@ -238,3 +241,11 @@ def pr_parareal_iteration(h):
 
 def pr_parareal_destroy(h):
     _check(lib().pr_parareal_destroy(h))
+
+
+def pr_parareal_profile(h):
+    """{phase name: summed device ms}, number of timed iterations."""
+    arr = (_c_dbl * len(PHASES))()
+    it = _c_int()
+    _check(lib().pr_parareal_profile(h, arr, ctypes.byref(it)))
+    return dict(zip(PHASES, list(arr))), it.value

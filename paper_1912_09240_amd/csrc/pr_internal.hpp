@@ -10,6 +10,7 @@
 #include <string>
 
 #include "pr.h"
+#include "pr_fastmath.hpp"
 
 namespace pr {
 
@@ -71,27 +72,40 @@ __host__ __device__ inline int64_t slice_begin(int64_t S, int N, int n) {
 // ---------------------------------------------------------------------------
 // Noise.  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
 //   (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
-// with the key advanced by the Weyl increments between rounds.
+// with the key advanced by the Weyl increments (k0 + r W0, k1 + r W1 in
+// round r).
 // ---------------------------------------------------------------------------
 struct Block {
     uint32_t w0, w1, w2, w3;
 };
 
+// One round.  XOR3 selects a single three-input VALU xor for the words that
+// vary across lanes; for the counter layout used here (only the particle
+// index varies inside a wave) the first rounds mix mostly wave-uniform words,
+// which the compiler keeps on the scalar unit.
+template <bool XOR3_0, bool XOR3_2>
+__device__ __forceinline__ void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                             uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
+    const uint32_t n0 = XOR3_0 ? __builtin_amdgcn_bitop3_b32(h1, c1, k0, 0x96) : (h1 ^ c1 ^ k0);
+    const uint32_t n2 = XOR3_2 ? __builtin_amdgcn_bitop3_b32(h0, c3, k1, 0x96) : (h0 ^ c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+}
+
 __device__ __forceinline__ Block philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    philox_round<false, false>(c0, c1, c2, c3, k0, k1);
+    philox_round<false, false>(c0, c1, c2, c3, k0 + W0, k1 + W1);
+    philox_round<false, false>(c0, c1, c2, c3, k0 + 2 * W0, k1 + 2 * W1);
+    philox_round<true, false>(c0, c1, c2, c3, k0 + 3 * W0, k1 + 3 * W1);
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
+    for (uint32_t r = 4; r < 10; ++r) philox_round<true, true>(c0, c1, c2, c3, k0 + r * W0, k1 + r * W1);
     return Block{c0, c1, c2, c3};
 }
 
@@ -114,13 +128,14 @@ __device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u
 }
 
 // Box-Muller: z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 log u1).
-// The angle goes through sincospi, so no range reduction by 2 pi is needed.
+// The angle 2 pi u2 = (pi/2)(4 u2) is reduced by quadrants of the exact
+// argument 4 u2, so no range reduction by 2 pi is needed.
 __device__ __forceinline__ void box_muller(const Block &b, double &z0, double &z1) {
     double u1, u2;
     uniforms53(b, u1, u2);
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt_pos(-2.0 * log_unit(u1));
     double s, c;
-    sincospi(2.0 * u2, &s, &c);
+    sincos_quarter(4.0 * u2, s, c);
     z0 = r * c;
     z1 = r * s;
 }

@@ -43,6 +43,9 @@ struct Parareal {
     size_t ws_bytes = 0;
     int cur = 0;
     int k = 0;
+    hipEvent_t ev[PR_PH_COUNT + 1] = {};
+    double ph_ms[PR_PH_COUNT] = {};
+    int timed = 0;
 
     char *xs(int b, int t) const { return x[b] + (size_t)t * n * esz; }
     char *ys(int b, int t) const { return y[b] + (size_t)t * D * n * esz; }
@@ -56,6 +59,8 @@ static void parareal_free(Parareal *h) {
                     h->rank, h->err, h->ws};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (hipEvent_t e : h->ev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -140,6 +145,9 @@ int parareal_create(const pr_sde *sde_in, const pr_schedule *sch, const pr_grid 
     h->ws_bytes = restrict_ws(n, K + 1, h->sde.precision);
     PR_ALLOC(h->ws, h->ws_bytes);
     PR_TRY(coarse_create(&h->sde, sch, grid, st, &h->coarse));
+    if (flags & PR_PROFILE)
+        for (hipEvent_t &e : h->ev)
+            PR_TRY(hipEventCreate(&e) == hipSuccess ? PR_OK : PR_E_HIP);
 
     // initial ensemble in slot 0 of both buffers
     PR_TRY(init_ensemble(&h->sde, seed, inst, n, h->xs(0, 0), h->ys(0, 0), st));
@@ -171,8 +179,14 @@ int parareal_create(const pr_sde *sde_in, const pr_schedule *sch, const pr_grid 
 int parareal_iterate(Parareal *h, int n_iter, const double *q_ref, double *err_out, hipStream_t st) {
     const int K = h->K, Q = h->Q;
     const int64_t n = h->n;
+    const bool prof = (h->flags & PR_PROFILE) != 0;
+    auto mark = [&](int i) -> int {
+        if (prof) PR_HIP(hipEventRecord(h->ev[i], st));
+        return PR_OK;
+    };
     for (int it = 0; it < n_iter; ++it) {
         const int c = h->cur, nx = 1 - c;
+        PR_CHECK(mark(0));
         // 1. fine: slice s reads X_k^s from buffer c, writes Xbar^{s+1} into buffer nx
         int first = 0;
         if (h->flags & PR_SKIP_CONVERGED) {
@@ -185,21 +199,26 @@ int parareal_iterate(Parareal *h, int n_iter, const double *q_ref, double *err_o
         }
         PR_CHECK(fine_propagate(&h->sde, &h->sch, h->seed, h->inst, n, first, K - first, h->xs(c, first),
                                 h->ys(c, first), h->xs(nx, first + 1), h->ys(nx, first + 1), st));
+        PR_CHECK(mark(1));
         // 2. restriction of the fine results: q_f^{s+1}, ranks
         PR_CHECK(restrict_quantiles(h->xs(nx, 1), h->sde.precision, n, K, Q, nullptr, h->qrow(h->qf, 1), h->rank,
                                     nullptr, nullptr, nullptr, nullptr, h->ws, st));
+        PR_CHECK(mark(2));
         // 3. coarse propagation of every slice from the previous states
         const double *cin = (h->flags & PR_REUSE_COARSE) ? h->q : h->qR;
         PR_CHECK(coarse_step(h->coarse, 0, K, cin, Q + 1, h->qrow(h->qcs, 1), Q + 1, nullptr, st));
+        PR_CHECK(mark(3));
         // 4. serial chain
         PR_HIP(hipMemcpyAsync(h->qn, h->q, sizeof(double) * (Q + 1), hipMemcpyDeviceToDevice, st));
         for (int s = 0; s < K; ++s)
             PR_CHECK(coarse_jump(h->coarse, s, h->qrow(h->qn, s), h->qrow(h->qf, s + 1), h->qrow(h->qcs, s + 1),
                                  h->qrow(h->qn, s + 1), nullptr, st));
+        PR_CHECK(mark(4));
         // 5. matching of the fine results, in place
         MatchArgs ma{h->qrow(h->qn, 1), Q + 1, h->qrow(h->qf, 1), Q + 1, h->rank, n, h->xs(nx, 1), n,
                      h->xs(nx, 1), n};
         PR_CHECK(match_strided(ma, n, K, Q, h->sde.precision, st));
+        PR_CHECK(mark(5));
         std::swap(h->q, h->qn);
         // 6. knots of the new states
         PR_CHECK(restrict_states(h, nx, 1, K, st));
@@ -208,10 +227,20 @@ int parareal_iterate(Parareal *h, int n_iter, const double *q_ref, double *err_o
         if (q_ref) {
             hipLaunchKernelGGL(knot_error, dim3(1), dim3(256), 0, st, (const double *)h->qR, q_ref, K, Q, h->err);
             PR_LAUNCHED();
-            if (err_out) {
-                PR_HIP(hipMemcpyAsync(err_out + 2 * it, h->err, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
-                PR_HIP(hipStreamSynchronize(st));
+        }
+        PR_CHECK(mark(6));
+        if (q_ref && err_out) {
+            PR_HIP(hipMemcpyAsync(err_out + 2 * it, h->err, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+            PR_HIP(hipStreamSynchronize(st));
+        }
+        if (prof) {
+            PR_HIP(hipEventSynchronize(h->ev[PR_PH_COUNT]));
+            for (int p = 0; p < PR_PH_COUNT; ++p) {
+                float ms = 0.f;
+                PR_HIP(hipEventElapsedTime(&ms, h->ev[p], h->ev[p + 1]));
+                h->ph_ms[p] += ms;
             }
+            h->timed += 1;
         }
     }
     return PR_OK;
@@ -230,7 +259,7 @@ extern "C" int pr_parareal_create(const pr_sde *sde, const pr_schedule *sched, c
     PR_REQUIRE(h != nullptr, "h is NULL");
     PR_REQUIRE(n >= 1 && n <= 0xFFFFFFFFll, "n must be in [1, 2^32)");
     PR_REQUIRE(sched->n_slices <= 1023, "at most 1023 slices");
-    PR_REQUIRE((flags & ~(PR_REUSE_COARSE | PR_SKIP_CONVERGED)) == 0, "unknown flags");
+    PR_REQUIRE((flags & ~(PR_REUSE_COARSE | PR_SKIP_CONVERGED | PR_PROFILE)) == 0, "unknown flags");
     Parareal *p = nullptr;
     PR_CHECK(parareal_create(sde, sched, grid, seed, instance, n, flags, as_stream(stream), &p));
     *h = p;
@@ -258,6 +287,16 @@ extern "C" int pr_parareal_state(void *hv, int t, void *x, void *y, double *q, v
 }
 
 extern "C" int pr_parareal_iteration(const void *h) { return h ? ((const Parareal *)h)->k : -1; }
+
+extern "C" int pr_parareal_profile(const void *hv, double *ms_out, int *iterations) {
+    clear_error();
+    PR_REQUIRE(hv != nullptr && ms_out != nullptr, "h and ms_out must be non-NULL");
+    const Parareal *h = (const Parareal *)hv;
+    PR_REQUIRE(h->flags & PR_PROFILE, "handle was created without PR_PROFILE");
+    for (int p = 0; p < PR_PH_COUNT; ++p) ms_out[p] = h->ph_ms[p];
+    if (iterations) *iterations = h->timed;
+    return PR_OK;
+}
 
 extern "C" int pr_parareal_destroy(void *h) {
     clear_error();
