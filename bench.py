@@ -81,6 +81,59 @@ def cpu_baseline(n_sample):
                        f"0..{n_sample - 1}; {t:.2f} s on {threads} OpenMP threads")
 
 
+ADJOINT = dict(lam=1.0, beta=2.0, eps=0.1, c3=1.0, n=2 ** 20, S=10_000, dt=1e-4, every=256, seed=0,
+               alpha=(0.1, 0.5, 0.9))
+
+
+def adjoint_measure(torch, pr):
+    """Differentiated form: P = 2^20, 1e4 steps of dt = 1e-4, checkpoints every
+    256 steps, observables mean X_T^2 and the 0.1/0.5/0.9 quantiles, all four
+    rows of the Jacobian w.r.t. (lambda, eps, beta, c3) in one reverse sweep.
+    Times (HIP events on the current stream): forward with checkpoints,
+    observables, reverse sweep; and a plain forward for the comparison with
+    8 common-random-number finite-difference runs."""
+    a = ADJOINT
+    n, S, dt, every = a["n"], a["S"], a["dt"], a["every"]
+    sde = pr.Sde(lam=a["lam"], eps=a["eps"], beta=a["beta"], c3=a["c3"])
+    sched = pr.Schedule(S, 1, dt)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ck = torch.empty(((S + every - 1) // every, 2, n), dtype=torch.float64, device="cuda")
+    k = 1 + len(a["alpha"])
+    obs = torch.empty(k, dtype=torch.float64, device="cuda")
+    seeds = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    wso = torch.empty(pr.pr_observables_workspace_size(n), dtype=torch.uint8, device="cuda")
+    jac = torch.empty((k, 4), dtype=torch.float64, device="cuda")
+    wsa = torch.empty(pr.pr_adjoint_workspace_size(n, every, k), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for rep in range(2):  # second repetition is the measured one
+        pr.pr_init_ensemble(sde, a["seed"], 0, n, x, y)
+        ev[0].record()
+        pr.pr_fine_checkpoint(sde, sched, a["seed"], 0, n, x, y, ck, every)
+        ev[1].record()
+        pr.pr_observables(x, n, list(a["alpha"]), obs, wso, seed_x=seeds)
+        ev[2].record()
+        pr.pr_fine_adjoint(sde, sched, a["seed"], 0, n, ck, every, seeds, k, jac, wsa)
+        ev[3].record()
+        pr.pr_init_ensemble(sde, a["seed"], 0, n, x, y)
+        ev[4].record()
+        pr.pr_fine_propagate(sde, sched, a["seed"], 0, n, 0, 1, x, y)
+        ev[5].record()
+        torch.cuda.synchronize()
+    t_fwd = ev[0].elapsed_time(ev[1]) / 1e3
+    t_obs = ev[1].elapsed_time(ev[2]) / 1e3
+    t_adj = ev[2].elapsed_time(ev[3]) / 1e3
+    t_plain = ev[4].elapsed_time(ev[5]) / 1e3
+    total = t_fwd + t_obs + t_adj
+    return dict(workload="adjoint of the 2-D SDE (lambda=1, beta=2, eps=0.1), P=2^20 FP64, 1e4 steps of dt=1e-4, "
+                         "checkpoints every 256 steps, observables mean X_T^2 and quantiles 0.1/0.5/0.9, "
+                         "4x4 Jacobian w.r.t. (lambda, eps, beta, c3) in one reverse sweep",
+                fwd_plus_adjoint_particle_steps_per_s=n * S / total, forward_ckpt_s=t_fwd, observables_s=t_obs,
+                reverse_s=t_adj, plain_forward_s=t_plain,
+                ratio_to_8_crn_fd_forwards=total / (8 * t_plain),
+                jacobian=jac.cpu().tolist(), observables=obs.cpu().tolist())
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +217,8 @@ def main():
                quantile_error=dict(at_T=[float(errs[2 * i]) for i in range(args.warmup + args.steps)],
                                    max_over_slices=[float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]),
                serial_fine_s=t_serial, create_s=t_create)
+    log("adjoint")
+    out["adjoint"] = adjoint_measure(torch, pr)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -221,6 +221,41 @@ int pr_parareal_iteration(const void *h);
 int pr_parareal_profile(const void *h, double *ms_out, int *iterations);
 int pr_parareal_destroy(void *h);
 
+/*
+ * Pathwise adjoint of the fine propagator (d = 1, FP64, a = NULL) with
+ * respect to theta = (lambda, eps, beta, c3), noise held fixed (the same
+ * Philox numbers), for observables of the slow variable at the final step.
+ *
+ * pr_fine_checkpoint: Euler-Maruyama over all global steps [0, S) of sched
+ *   (its slice count is ignored) from the state in x, y ([n] each, updated in
+ *   place to step S), writing the state at steps 0, E, 2E, ... into
+ *   ckpt [ceil(S/E)][2][n] (x then y), E = ckpt_every.
+ * pr_observables: obs[0] = (1/n) sum x^2; obs[1+a] = midpoint (Hazen)
+ *   quantile of x at level alpha[a] (host, a < n_alpha <= 3).  If seed_x is
+ *   given ([1+n_alpha][n]) it receives d obs / d x_p with the order frozen:
+ *   2 x_p / n, and (1-f), f at the two order statistics of a quantile.
+ * pr_fine_adjoint: reverse sweep over the checkpointed trajectory.  Segments
+ *   are replayed from their checkpoints (the noise regenerated from Philox),
+ *   with states every 8 steps kept in the workspace and 8-step tapes in
+ *   registers; the per-step noise increments are recovered from consecutive
+ *   states.  seed_x (and seed_y or NULL) [n_seed][n] are dL_k/dX_S,
+ *   dL_k/dY_S; grad [n_seed][4] (device) receives dL_k/d(lambda, eps, beta,
+ *   c3).  from_initial != 0 adds the dependence of the initial law
+ *   Y0 = X0 + beta^-1/2 z on beta (the checkpoint at step 0 must then be the
+ *   initial ensemble of pr_init_ensemble).  n_seed <= 4.  Workspace:
+ *   pr_adjoint_workspace_size bytes.  Other d or precisions: PR_E_UNSUPPORTED.
+ */
+int pr_fine_checkpoint(const pr_sde *sde, const pr_schedule *sched, uint64_t seed, uint32_t instance,
+                       int64_t n, void *x, void *y, double *ckpt, int ckpt_every, void *stream);
+size_t pr_observables_workspace_size(int64_t n);
+int pr_observables(const double *x, int64_t n, const double *alpha, int n_alpha, double *obs,
+                   double *seed_x, void *ws, size_t ws_bytes, void *stream);
+size_t pr_adjoint_workspace_size(int64_t n, int ckpt_every, int n_seed);
+int pr_fine_adjoint(const pr_sde *sde, const pr_schedule *sched, uint64_t seed, uint32_t instance,
+                    int64_t n, const double *ckpt, int ckpt_every, const double *seed_x,
+                    const double *seed_y, int n_seed, int from_initial, double *grad, void *ws,
+                    size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,8 @@ __all__ = [
     "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy",
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
     "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
-    "PR_PROFILE", "PHASES",
+    "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
+    "pr_adjoint_workspace_size", "pr_fine_adjoint",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -108,6 +109,13 @@ _SIGS = {
     "pr_parareal_iteration": (_c_int, [_vp]),
     "pr_parareal_destroy": (_c_int, [_vp]),
     "pr_parareal_profile": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_int)]),
+    "pr_fine_checkpoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64,
+                                    _vp, _vp, _vp, _c_int, _vp]),
+    "pr_observables_workspace_size": (ctypes.c_size_t, [_c_i64]),
+    "pr_observables": (_c_int, [_vp, _c_i64, ctypes.POINTER(_c_dbl), _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_adjoint_workspace_size": (ctypes.c_size_t, [_c_i64, _c_int, _c_int]),
+    "pr_fine_adjoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64, _vp,
+                                 _c_int, _vp, _vp, _c_int, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
 }
 
 
@@ -249,3 +257,33 @@ def pr_parareal_profile(h):
     it = _c_int()
     _check(lib().pr_parareal_profile(h, arr, ctypes.byref(it)))
     return dict(zip(PHASES, list(arr))), it.value
+
+
+def pr_fine_checkpoint(sde, sched, seed, instance, n, x, y, ckpt, ckpt_every, stream=None):
+    s, c = sde.c(), sched.c()
+    _check(lib().pr_fine_checkpoint(ctypes.byref(s), ctypes.byref(c), seed, instance, n, _ptr(x), _ptr(y),
+                                    _ptr(ckpt), ckpt_every, _stream(stream)))
+
+
+def pr_observables_workspace_size(n):
+    return lib().pr_observables_workspace_size(n)
+
+
+def pr_observables(x, n, alpha, obs, ws, seed_x=None, stream=None):
+    a = (_c_dbl * max(1, len(alpha)))(*alpha)
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().pr_observables(_ptr(x), n, a, len(alpha), _ptr(obs), _ptr(seed_x), _ptr(ws), nbytes,
+                                _stream(stream)))
+
+
+def pr_adjoint_workspace_size(n, ckpt_every, n_seed):
+    return lib().pr_adjoint_workspace_size(n, ckpt_every, n_seed)
+
+
+def pr_fine_adjoint(sde, sched, seed, instance, n, ckpt, ckpt_every, seed_x, n_seed, grad, ws, seed_y=None,
+                    from_initial=True, stream=None):
+    s, c = sde.c(), sched.c()
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().pr_fine_adjoint(ctypes.byref(s), ctypes.byref(c), seed, instance, n, _ptr(ckpt), ckpt_every,
+                                 _ptr(seed_x), _ptr(seed_y), n_seed, 1 if from_initial else 0, _ptr(grad), _ptr(ws),
+                                 nbytes, _stream(stream)))
