@@ -49,8 +49,17 @@ enum {
     PR_REUSE_COARSE = 1,   /* q_c^* = C(q_k^n) instead of C(R(X_k^n))          */
     PR_SKIP_CONVERGED = 2, /* do not re-run the fine propagator on slices whose
                               start is already exact (n < k, Sec. 3.3.3)       */
-    PR_PROFILE = 4         /* record HIP events around each phase of an
+    PR_PROFILE = 4,        /* record HIP events around each phase of an
                               iteration (see pr_parareal_profile)              */
+    PR_AUTOTUNE = 8        /* batched handle: time the fine kernel's shapes at
+                              creation and keep the fastest                    */
+};
+
+/* Launch patterns of pr_parareal_batch_iterate (same results bitwise). */
+enum {
+    PR_LAUNCH_BATCHED = 0,      /* one launch per phase for all instances       */
+    PR_LAUNCH_GRAPH = 1,        /* the batched sequence captured in a hipGraph   */
+    PR_LAUNCH_PER_INSTANCE = 2  /* every phase launched instance by instance     */
 };
 
 /* Phases reported by pr_parareal_profile. */
@@ -220,6 +229,38 @@ int pr_parareal_iteration(const void *h);
  * fails with PR_E_INVALID. */
 int pr_parareal_profile(const void *h, double *ms_out, int *iterations);
 int pr_parareal_destroy(void *h);
+
+/*
+ * Batched micro-macro parareal over many independent instances (d = 1, FP64,
+ * a = NULL), each with its own SDE parameters, particle count n[i] and
+ * schedule, sharing the coarse grid.  Host arrays sde, sched, n have n_inst
+ * entries; instance (host, may be NULL for 0..n_inst-1) gives the Philox
+ * instance word of each.  Creation draws every initial ensemble, builds the
+ * coarse exponentials of every distinct slice length and runs the zeroth
+ * iteration (synchronous).  flags: PR_REUSE_COARSE, PR_AUTOTUNE.
+ * pr_parareal_batch_iterate runs n_iter iterations with the given launch
+ * pattern; ms_out (host, may be NULL) receives their device time (HIP events
+ * on stream; the call then waits for them).  The fine propagation of all
+ * slices of all instances is one persistent launch whose workgroups take
+ * (instance, slice, particle tile) units from a queue in decreasing cost.
+ * pr_parareal_batch_state copies the state of instance inst at time t.
+ * pr_parareal_batch_info reports the tuned block size and particles per
+ * thread, the number of fine work units and the fine particle-steps of one
+ * iteration.  pr_draw_instances writes, for instances 0..count-1, the
+ * batched-workload draw of (eps, lambda, log2 n, slices) from the tag-3
+ * block of each: eps = 10^(-3+2u0), lambda = 0.5+1.5u1, log2 n =
+ * 12+floor(7u2), slices = 8+floor(57u3), u_k = (w_k + 1/2) 2^-32.
+ * out: device [count][4].
+ */
+int pr_draw_instances(uint64_t seed, int count, double *out, void *stream);
+int pr_parareal_batch_create(int n_inst, const pr_sde *sde, const pr_schedule *sched, const int64_t *n,
+                             const pr_grid *grid, uint64_t seed, const uint32_t *instance, int flags,
+                             void *stream, void **h);
+int pr_parareal_batch_iterate(void *h, int n_iter, int mode, double *ms_out, void *stream);
+int pr_parareal_batch_state(void *h, int inst, int t, void *x, void *y, double *q, void *stream);
+int pr_parareal_batch_info(const void *h, int *tuned_block, int *tuned_ppt, int64_t *units,
+                           int64_t *particle_steps);
+int pr_parareal_batch_destroy(void *h);
 
 /*
  * Pathwise adjoint of the fine propagator (d = 1, FP64, a = NULL) with

@@ -18,14 +18,17 @@ __all__ = [
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
     "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
     "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
-    "pr_adjoint_workspace_size", "pr_fine_adjoint",
+    "pr_adjoint_workspace_size", "pr_fine_adjoint", "pr_draw_instances", "pr_parareal_batch_create",
+    "pr_parareal_batch_iterate", "pr_parareal_batch_state", "pr_parareal_batch_info", "pr_parareal_batch_destroy",
+    "PR_AUTOTUNE", "PR_LAUNCH_BATCHED", "PR_LAUNCH_GRAPH", "PR_LAUNCH_PER_INSTANCE",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_F64, PR_F32 = 64, 32
-PR_REUSE_COARSE, PR_SKIP_CONVERGED, PR_PROFILE = 1, 2, 4
+PR_REUSE_COARSE, PR_SKIP_CONVERGED, PR_PROFILE, PR_AUTOTUNE = 1, 2, 4, 8
+PR_LAUNCH_BATCHED, PR_LAUNCH_GRAPH, PR_LAUNCH_PER_INSTANCE = 0, 1, 2
 PHASES = ("fine", "restrict_fine", "coarse", "chain", "match", "restrict_new")
 
 _c_int, _c_i64, _c_u32, _c_u64, _c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
@@ -114,6 +117,14 @@ _SIGS = {
     "pr_observables_workspace_size": (ctypes.c_size_t, [_c_i64]),
     "pr_observables": (_c_int, [_vp, _c_i64, ctypes.POINTER(_c_dbl), _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "pr_adjoint_workspace_size": (ctypes.c_size_t, [_c_i64, _c_int, _c_int]),
+    "pr_draw_instances": (_c_int, [_c_u64, _c_int, _vp, _vp]),
+    "pr_parareal_batch_create": (_c_int, [_c_int, _vp, _vp, _vp, ctypes.POINTER(_CGrid), _c_u64, _vp, _c_int, _vp,
+                                          ctypes.POINTER(_vp)]),
+    "pr_parareal_batch_iterate": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_dbl), _vp]),
+    "pr_parareal_batch_state": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
+    "pr_parareal_batch_info": (_c_int, [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_i64),
+                                        ctypes.POINTER(_c_i64)]),
+    "pr_parareal_batch_destroy": (_c_int, [_vp]),
     "pr_fine_adjoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64, _vp,
                                  _c_int, _vp, _vp, _c_int, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
 }
@@ -287,3 +298,43 @@ def pr_fine_adjoint(sde, sched, seed, instance, n, ckpt, ckpt_every, seed_x, n_s
     _check(lib().pr_fine_adjoint(ctypes.byref(s), ctypes.byref(c), seed, instance, n, _ptr(ckpt), ckpt_every,
                                  _ptr(seed_x), _ptr(seed_y), n_seed, 1 if from_initial else 0, _ptr(grad), _ptr(ws),
                                  nbytes, _stream(stream)))
+
+
+def pr_draw_instances(seed, count, out, stream=None):
+    """out: device float64 tensor [count][4] <- (eps, lambda, log2 n, slices)."""
+    _check(lib().pr_draw_instances(seed, count, _ptr(out), _stream(stream)))
+
+
+def pr_parareal_batch_create(sdes, scheds, ns, grid, seed, instances=None, flags=0, stream=None):
+    B = len(sdes)
+    S = (_CSde * B)(*[s.c() for s in sdes])
+    C = (_CSchedule * B)(*[c.c() for c in scheds])
+    N = (_c_i64 * B)(*ns)
+    ids = (_c_u32 * B)(*instances) if instances is not None else None
+    g = grid.c()
+    h = _vp()
+    _check(lib().pr_parareal_batch_create(B, ctypes.cast(S, _vp), ctypes.cast(C, _vp), ctypes.cast(N, _vp),
+                                          ctypes.byref(g), seed, ctypes.cast(ids, _vp) if ids is not None else None,
+                                          flags, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_batch_iterate(h, n_iter, mode=PR_LAUNCH_BATCHED, timed=False, stream=None):
+    """Returns the device time of the iterations in ms when timed."""
+    ms = _c_dbl(0.0)
+    _check(lib().pr_parareal_batch_iterate(h, n_iter, mode, ctypes.byref(ms) if timed else None, _stream(stream)))
+    return ms.value if timed else None
+
+
+def pr_parareal_batch_state(h, inst, t, x=None, y=None, q=None, stream=None):
+    _check(lib().pr_parareal_batch_state(h, inst, t, _ptr(x), _ptr(y), _ptr(q), _stream(stream)))
+
+
+def pr_parareal_batch_info(h):
+    b, p, u, w = _c_int(), _c_int(), _c_i64(), _c_i64()
+    _check(lib().pr_parareal_batch_info(h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(u), ctypes.byref(w)))
+    return dict(block=b.value, ppt=p.value, units=u.value, particle_steps=w.value)
+
+
+def pr_parareal_batch_destroy(h):
+    _check(lib().pr_parareal_batch_destroy(h))

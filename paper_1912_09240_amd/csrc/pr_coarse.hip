@@ -13,6 +13,7 @@
 #include <cmath>
 #include <vector>
 
+#include "pr_coarse_dev.hpp"
 #include "pr_internal.hpp"
 
 namespace pr {
@@ -77,36 +78,6 @@ __global__ void tridiag_to_dense(const double *__restrict__ lo, const double *__
     X[e] = v;
 }
 
-// ---------------------------------------------------------------------------
-// Knots -> cell masses (H).  c(x) = 0 for x <= q_0, 1 for x > q_Q, else
-// (j + (x - q_j)/(q_{j+1} - q_j))/Q with j the largest index with q_j < x
-// (a repeated knot is a jump; c(x) = P(X < x)).  rho_i = c(x_{i+1}) - c(x_i),
-// the mass beyond the grid going to the end cells.
-// ---------------------------------------------------------------------------
-struct GridDev {
-    int cells, nq;
-    double lo, h;
-};
-
-__device__ __forceinline__ double edge_at(const GridDev &g, int i) {
-#pragma clang fp contract(off)
-    return g.lo + (double)i * g.h;
-}
-
-__device__ double cdf_knots(const double *q, int nq, double x) {
-#pragma clang fp contract(off)
-    if (x <= q[0]) return 0.0;
-    if (x > q[nq]) return 1.0;
-    int lo = 0, hi = nq;  // q[lo] < x <= q[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (q[mid] < x) lo = mid;
-        else hi = mid;
-    }
-    const double t = (x - q[lo]) / (q[lo + 1] - q[lo]);
-    return ((double)lo + t) / (double)nq;
-}
-
 __global__ void __launch_bounds__(256) knots_to_masses(const double *__restrict__ q, int q_stride,
                                                        double *__restrict__ rho, GridDev g) {
 #pragma clang fp contract(off)
@@ -151,57 +122,6 @@ __global__ void __launch_bounds__(256) apply_expm(const double *__restrict__ E, 
     }
 }
 
-// Cell masses -> knots (Qf) of the piecewise-linear cdf with cumulative
-// masses C_i (left to right); level p_j C_I.  A level hit on a flat stretch
-// gives its midpoint; the end knots are the grid ends.  Runs inside one
-// block; C must hold cells + 1 doubles of LDS.
-__device__ void masses_to_knots_block(const double *rho, double *C, const GridDev &g, double *q) {
-#pragma clang fp contract(off)
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        C[0] = 0.0;
-        for (int i = 0; i < g.cells; ++i) {
-            acc = acc + rho[i];
-            C[i + 1] = acc;
-        }
-    }
-    __syncthreads();
-    const double tot = C[g.cells];
-    for (int j = threadIdx.x; j <= g.nq; j += blockDim.x) {
-        double v;
-        if (j == 0) {
-            v = edge_at(g, 0);
-        } else if (j == g.nq) {
-            v = edge_at(g, g.cells);
-        } else {
-            const double ct = ((double)j / (double)g.nq) * tot;
-            int lo = -1, hi = g.cells;  // first i with C_i >= ct: C[lo] < ct <= C[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (C[mid] >= ct) hi = mid;
-                else lo = mid;
-            }
-            const int i1 = hi;
-            if (C[i1] > ct) {
-                const int i = i1 - 1;
-                const double e0 = edge_at(g, i), e1 = edge_at(g, i + 1);
-                double x = e0 + (ct - C[i]) / rho[i] * g.h;
-                x = x > e0 ? x : e0;
-                v = x < e1 ? x : e1;
-            } else {
-                int lo2 = i1, hi2 = g.cells + 1;  // last i with C_i <= ct: C[lo2] <= ct < C[hi2]
-                while (hi2 - lo2 > 1) {
-                    const int mid = (lo2 + hi2) >> 1;
-                    if (C[mid] <= ct) lo2 = mid;
-                    else hi2 = mid;
-                }
-                v = 0.5 * (edge_at(g, i1) + edge_at(g, lo2));
-            }
-        }
-        q[j] = v;
-    }
-}
-
 __global__ void __launch_bounds__(256) masses_to_knots(const double *__restrict__ rho, double *__restrict__ q,
                                                        int q_stride, GridDev g) {
     extern __shared__ double sh[];
@@ -211,29 +131,6 @@ __global__ void __launch_bounds__(256) masses_to_knots(const double *__restrict_
     for (int i = threadIdx.x; i < g.cells; i += blockDim.x) r[i] = rho[(int64_t)s * g.cells + i];
     __syncthreads();
     masses_to_knots_block(r, C, g, q + (int64_t)s * q_stride);
-}
-
-// Pool-adjacent-violators (equal weights), single thread, in place; L <= cap.
-__device__ void pava_serial(double *v, int L, double *S, int *Cn) {
-#pragma clang fp contract(off)
-    int nb = 0;
-    for (int i = 0; i < L; ++i) {
-        double s = v[i];
-        int c = 1;
-        while (nb > 0 && S[nb - 1] / (double)Cn[nb - 1] > s / (double)c) {
-            s += S[nb - 1];
-            c += Cn[nb - 1];
-            --nb;
-        }
-        S[nb] = s;
-        Cn[nb] = c;
-        ++nb;
-    }
-    int o = 0;
-    for (int b = 0; b < nb; ++b) {
-        const double m = S[b] / (double)Cn[b];
-        for (int t = 0; t < Cn[b]; ++t) v[o++] = m;
-    }
 }
 
 // Quantile iterator on fixed levels: q_new = PAVA(q_f + (q_c_next - q_c_star)).
@@ -276,7 +173,7 @@ struct Coarse {
     int device = 0;
 };
 
-static int build_expm(const std::vector<double> &lo, const std::vector<double> &di, const std::vector<double> &up,
+int build_expm(const std::vector<double> &lo, const std::vector<double> &di, const std::vector<double> &up,
                       int n, double tau, double *out, double *w1, double *w2, double *w3, hipStream_t st) {
     // ||A tau||_1 = max column sum of |entries|
     double norm = 0.0;
@@ -322,8 +219,10 @@ static int build_expm(const std::vector<double> &lo, const std::vector<double> &
     return PR_OK;
 }
 
-int coarse_create(const pr_sde *sde, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
-                  Coarse **out) {
+// Tridiagonal generator of the finite-volume scheme: lo[i] = A[i][i-1],
+// di[i] = A[i][i], up[i] = A[i][i+1].
+int make_generator(const pr_sde *sde, const pr_grid *grid, std::vector<double> &lo, std::vector<double> &di,
+                   std::vector<double> &up, hipStream_t st) {
     const int I = grid->n_cells;
     const double h = (grid->x_hi - grid->x_lo) / I;
     // effective potential V = c3 x^4/4 + k2 x^2/2, k2 = c1 + lambda (1 - mean a)
@@ -348,13 +247,23 @@ int coarse_create(const pr_sde *sde, const pr_schedule *sch, const pr_grid *grid
         const double e = grid->x_lo + i * h;
         a[i] = dbar * std::exp(-beta * V(e)) / h;
     }
-    // tridiagonal A: lo[i] = A[i][i-1], di[i] = A[i][i], up[i] = A[i][i+1]
-    std::vector<double> lo(I, 0.0), di(I), up(I, 0.0);
+    lo.assign(I, 0.0);
+    di.assign(I, 0.0);
+    up.assign(I, 0.0);
     for (int i = 0; i < I; ++i) {
         di[i] = -(a[i] + a[i + 1]) / g[i];
         if (i + 1 < I) up[i] = a[i + 1] / g[i + 1];
         if (i >= 1) lo[i] = a[i] / g[i - 1];
     }
+    return PR_OK;
+}
+
+int coarse_create(const pr_sde *sde, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
+                  Coarse **out) {
+    const int I = grid->n_cells;
+    const double h = (grid->x_hi - grid->x_lo) / I;
+    std::vector<double> lo, di, up;
+    PR_CHECK(make_generator(sde, grid, lo, di, up, st));
     Coarse *c = new Coarse();
     c->g = GridDev{I, grid->n_q, grid->x_lo, h};
     c->n_slices = sch->n_slices;

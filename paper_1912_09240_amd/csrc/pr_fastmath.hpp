@@ -51,6 +51,7 @@ __host__ __device__ __forceinline__ double mantissa_exponent(double u, int &e) {
 
 // ln u for u in (0, 1].
 __host__ __device__ __forceinline__ double log_unit(double u) {
+#pragma clang fp contract(off)
     int e;
     double m = mantissa_exponent(u, e);  // m in [1/2, 1)
     if (m < 0.7071067811865476) {
@@ -81,6 +82,7 @@ __host__ __device__ __forceinline__ double log_unit(double u) {
 
 // sqrt x for x >= 0 (0 gives 0).
 __host__ __device__ __forceinline__ double sqrt_pos(double x) {
+#pragma clang fp contract(off)
     const double y = rsq_seed(x > 0.0 ? x : 1.0);
     double g = x * y;      // ~ sqrt x
     double h = 0.5 * y;    // ~ 1 / (2 sqrt x)
@@ -96,6 +98,7 @@ __host__ __device__ __forceinline__ double sqrt_pos(double x) {
 
 // sin(pi t/2) -> s, cos(pi t/2) -> c, for t in [0, 4].
 __host__ __device__ __forceinline__ void sincos_quarter(double t, double &s, double &c) {
+#pragma clang fp contract(off)
     const double k = __builtin_rint(t);
     const double r = t - k;  // exact
     const double r2 = r * r;

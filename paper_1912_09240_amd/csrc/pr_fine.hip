@@ -3,58 +3,10 @@
 // one slice and keeps their state in registers for the whole slice; the
 // normal increments come from the counter-based generator, so no random
 // state is stored and a slice recomputed later sees the same numbers.
+#include "pr_fine_dev.hpp"
 #include "pr_internal.hpp"
 
 namespace pr {
-
-// Parameters of the scheme, precomputed on the host.
-template <typename T>
-struct EmCoef {
-    T c3, c1, lam;  // drift of X: c3 x^3 + c1 x + lam (x - ybar)
-    T dt;           // fine step
-    T rate;         // dt / eps
-    T sx;           // sqrt(2 dt / beta)
-    T sy;           // sqrt(2 dt / (beta eps))
-};
-
-template <typename T>
-__device__ __forceinline__ void normal_pair(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                            uint32_t p, uint32_t j, T &z0, T &z1);
-
-template <>
-__device__ __forceinline__ void normal_pair<double>(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                                    uint32_t p, uint32_t j, double &z0, double &z1) {
-    box_muller(noise_block(key, inst, tag, m, p, j), z0, z1);
-}
-template <>
-__device__ __forceinline__ void normal_pair<float>(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                                   uint32_t p, uint32_t j, float &z0, float &z1) {
-    box_muller_f32(noise_block(key, inst, tag, m, p, j), z0, z1);
-}
-
-// One Euler-Maruyama step of one particle, drift at the old state.
-template <int D, typename T>
-__device__ __forceinline__ void em_step(T &x, T (&y)[D], const T (&a)[D], const EmCoef<T> &c,
-                                        Key key, uint32_t inst, uint32_t m, uint32_t p) {
-    constexpr int NP = (D + 2) / 2;  // pairs of normals for 1 + D components
-    T z[2 * NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) normal_pair<T>(key, inst, 0u, m, p, (uint32_t)j, z[2 * j], z[2 * j + 1]);
-    T ybar;
-    if constexpr (D == 1) {
-        ybar = y[0];
-    } else {
-        T s = (T)0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) s += y[i];
-        ybar = s / (T)D;
-    }
-    const T fx = c.c3 * x * x * x + c.c1 * x + c.lam * (x - ybar);
-    const T xn = x - c.dt * fx + c.sx * z[0];
-#pragma unroll
-    for (int i = 0; i < D; ++i) y[i] = y[i] - c.rate * (y[i] - a[i] * x) + c.sy * z[i + 1];
-    x = xn;
-}
 
 template <int D, typename T, int PPT>
 __global__ void __launch_bounds__(256) fine_kernel(const T *xin, const T *yin, T *xout, T *yout, int64_t n,
@@ -122,19 +74,6 @@ __global__ void coupling_kernel(double *a, int d, Key key, uint32_t inst) {
     double u1, u2;
     uniforms53(noise_block(key, inst, 2u, 0u, (uint32_t)i, 0u), u1, u2);
     a[i] = 0.5 + u2;
-}
-
-template <typename T>
-static EmCoef<T> make_coef(const pr_sde *s, double dt) {
-    EmCoef<T> c;
-    c.c3 = (T)s->c3;
-    c.c1 = (T)s->c1;
-    c.lam = (T)s->lambda;
-    c.dt = (T)dt;
-    c.rate = (T)(dt / s->eps);
-    c.sx = (T)std::sqrt(2.0 * dt / s->beta);
-    c.sy = (T)std::sqrt(2.0 * dt / (s->beta * s->eps));
-    return c;
 }
 
 template <int D, typename T>

@@ -121,6 +121,7 @@ __device__ __forceinline__ Block noise_block(Key key, uint32_t inst, uint32_t ta
 
 // 53-bit uniforms: u1 in (0, 1] (never 0, so log is finite), u2 in [0, 1).
 __device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u2) {
+#pragma clang fp contract(off)
     const double a = (double)(b.w0 >> 5) * 67108864.0 + (double)(b.w1 >> 6);
     const double c = (double)(b.w2 >> 5) * 67108864.0 + (double)(b.w3 >> 6);
     u1 = (a + 0.5) * 0x1p-53;
@@ -131,6 +132,7 @@ __device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u
 // The angle 2 pi u2 = (pi/2)(4 u2) is reduced by quadrants of the exact
 // argument 4 u2, so no range reduction by 2 pi is needed.
 __device__ __forceinline__ void box_muller(const Block &b, double &z0, double &z1) {
+#pragma clang fp contract(off)
     double u1, u2;
     uniforms53(b, u1, u2);
     const double r = sqrt_pos(-2.0 * log_unit(u1));
@@ -198,6 +200,27 @@ int fine_propagate(const pr_sde *sde, const pr_schedule *sch, uint64_t seed, uin
                    void *y_out, hipStream_t st);
 int init_ensemble(const pr_sde *sde, uint64_t seed, uint32_t inst, int64_t n, void *x, void *y, hipStream_t st);
 
+// Segments of one sort call.  Equal lengths: segs == NULL, segment s starts
+// at s * n.  Unequal lengths: a segment table and the segment of every tile
+// (tiles ordered by segment).
+struct SortSeg {
+    int64_t base;   // element offset of the segment in the value/rank arrays
+    int64_t n;      // length
+    int64_t tile0;  // index of its first tile
+    int32_t nblk;   // number of tiles
+    int32_t qrow;   // knot row of the segment
+};
+struct SortLayout {
+    int64_t n;             // equal lengths: keys per segment
+    int nblk;              // equal lengths: tiles per segment
+    int nseg;
+    const SortSeg *segs;   // unequal lengths: device table [nseg]
+    const int *tile_seg;   // unequal lengths: device table [tiles]
+};
+int64_t sort_tiles(int64_t n);
+size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload);
+int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t total_keys, int64_t total_tiles,
+                      int nq, double *q, uint32_t *rank, void *ws, hipStream_t st);
 size_t restrict_ws(int64_t n, int k, int precision);
 int restrict_quantiles(const void *x, int precision, int64_t n, int k, int nq, const pr_grid *hg, double *q,
                        uint32_t *rank, uint32_t *perm, double *xs, double *mom, uint32_t *hist, void *ws,

@@ -1,27 +1,29 @@
 // Restriction to the empirical quantile function (Sec. 3.2.2, Sec. 4.4):
-// a segmented, stable LSD radix sort of the slow coordinates of k ensembles
-// (one segment per ensemble), followed by the midpoint (Hazen) knots; the
-// moments (eq. (MCestimator)) and the cell histogram (eq. (binning)) are
-// fused into the first read of the values.
+// a segmented, stable LSD radix sort of the slow coordinates of many
+// ensembles (one segment per ensemble, equal or unequal lengths), followed by
+// the midpoint (Hazen) knots; the moments (eq. (MCestimator)) and the cell
+// histogram (eq. (binning)) are fused into the first read of the values.
 //
 // Sort design (HBM bound): 8-bit digits, one pass per byte of the orderable
-// key.  A pass = count (digit histogram of each 4096-key tile) -> scan
-// (per segment, digit-major over tiles, so equal digits keep tile order) ->
-// scatter.  Inside a tile each wave ranks its 1024 keys in order with
-// ballot-based peer masks, which keeps the pass stable; the tile is then
-// staged in LDS in digit order so that each digit run is written to HBM as a
-// contiguous burst.  The first pass reads the FP64 values directly and uses
-// the particle index as payload; the last pass writes the outputs the caller
-// asked for (rank by scatter, perm and sorted values in order).
+// key.  A pass is
+//   count   digit histogram of every tile (ITEMS x 256 keys),
+//   rowscan one wave per (segment, digit): exclusive prefix of that digit's
+//           tile counts and the digit total of the segment,
+//   scatter stable rank of every key inside its tile (each wave ranks its
+//           keys in order with ballot-built peer masks), exclusive scan of
+//           the digit totals, then the tile is staged in LDS in digit order
+//           and every digit run is written to HBM as a contiguous burst.
+// Equal digits keep tile order, so every pass is stable and the sort orders
+// by (key, particle).  The first pass reads FP64 (or FP32) values directly
+// and generates the particle index as payload; the last pass writes the
+// outputs asked for (rank by scatter, perm and sorted values in order).  A
+// sort that only needs knots carries no payload.
 #include "pr_internal.hpp"
 
 namespace pr {
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_WAVE_KEYS = 64 * RS_ITEMS;      // 1024
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;   // 4096
 constexpr int RS_RADIX = 256;
 
 template <typename K> struct KeyTraits;
@@ -34,41 +36,102 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Exclusive prefix of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t *wtot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wtot[w];
+    __syncthreads();
+    return pre + inc - v;
+}
+
 struct HistArgs {
-    uint32_t *hist;  // [k][cells] or NULL
+    uint32_t *hist;  // [segments][cells] or NULL
     int cells;
     double lo, inv_h;
 };
 
+struct TileRef {
+    int seg, blk, nblk;
+    int64_t base, n, tile0;
+};
+
+template <bool VAR>
+__device__ __forceinline__ TileRef tile_ref(const SortLayout &L, int64_t t) {
+    TileRef r;
+    if constexpr (VAR) {
+        r.seg = L.tile_seg[t];
+        const SortSeg s = L.segs[r.seg];
+        r.blk = (int)(t - s.tile0);
+        r.nblk = s.nblk;
+        r.base = s.base;
+        r.n = s.n;
+        r.tile0 = s.tile0;
+    } else {
+        r.seg = (int)(t / L.nblk);
+        r.blk = (int)(t % L.nblk);
+        r.nblk = L.nblk;
+        r.base = (int64_t)r.seg * L.n;
+        r.n = L.n;
+        r.tile0 = (int64_t)r.seg * L.nblk;
+    }
+    return r;
+}
+
+template <bool VAR>
+__device__ __forceinline__ void seg_ref(const SortLayout &L, int s, int64_t &base, int64_t &n, int64_t &tile0,
+                                        int &nblk, int &qrow) {
+    if constexpr (VAR) {
+        const SortSeg g = L.segs[s];
+        base = g.base;
+        n = g.n;
+        tile0 = g.tile0;
+        nblk = g.nblk;
+        qrow = g.qrow;
+    } else {
+        base = (int64_t)s * L.n;
+        n = L.n;
+        tile0 = (int64_t)s * L.nblk;
+        nblk = L.nblk;
+        qrow = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Count: per-tile digit histogram.  Pass 0 also sums the four powers of x
-// (fixed-order per tile) and fills the cell histogram.
+// Count.
 // ---------------------------------------------------------------------------
-template <typename K, bool FIRST>
+template <typename K, int ITEMS, bool FIRST, bool VAR>
 __global__ void __launch_bounds__(RS_THREADS)
-rs_count(const void *__restrict__ src, int shift, int64_t n, int nblk, uint32_t *__restrict__ counts,
+rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__restrict__ counts,
          double *__restrict__ mom_part, HistArgs ha) {
     using V = typename KeyTraits<K>::V;
+    constexpr int WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
     __shared__ uint32_t h[RS_WAVES][RS_RADIX];
     __shared__ double wsum[RS_WAVES][4];
     extern __shared__ uint32_t cell_h[];
-    const int seg = blockIdx.y, blk = blockIdx.x;
+    const TileRef T = tile_ref<VAR>(L, blockIdx.x);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < RS_WAVES * RS_RADIX; i += RS_THREADS) (&h[0][0])[i] = 0;
     const bool do_hist = FIRST && ha.hist != nullptr;
     if (do_hist)
         for (int i = tid; i < ha.cells; i += RS_THREADS) cell_h[i] = 0;
     __syncthreads();
-    const int64_t seg_base = (int64_t)seg * n;
-    const int64_t tile0 = (int64_t)blk * RS_TILE + wave * RS_WAVE_KEYS;
+    const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
 #pragma unroll 4
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        const int64_t idx = tile0 + i * 64 + lane;
-        if (idx < n) {
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        if (idx < T.n) {
             K key;
             if constexpr (FIRST) {
-                const V v = ((const V *)src)[seg_base + idx];
+                const V v = ((const V *)src)[T.base + idx];
                 key = key_of(v);
                 const double xv = (double)v;
                 const double x2 = xv * xv;
@@ -82,14 +145,13 @@ rs_count(const void *__restrict__ src, int shift, int64_t n, int nblk, uint32_t 
                     atomicAdd(&cell_h[(int)c], 1u);
                 }
             } else {
-                key = ((const K *)src)[seg_base + idx];
+                key = ((const K *)src)[T.base + idx];
             }
             atomicAdd(&h[wave][(uint32_t)(key >> shift) & 0xFFu], 1u);
         }
     }
     if (FIRST && mom_part != nullptr) {
-        // fixed butterfly: every lane ends with the same total
-        for (int off = 32; off >= 1; off >>= 1) {
+        for (int off = 32; off >= 1; off >>= 1) {  // fixed butterfly
             s1 += __shfl_xor(s1, off);
             s2 += __shfl_xor(s2, off);
             s3 += __shfl_xor(s3, off);
@@ -108,103 +170,93 @@ rs_count(const void *__restrict__ src, int shift, int64_t n, int nblk, uint32_t 
         uint32_t c = 0;
 #pragma unroll
         for (int w = 0; w < RS_WAVES; ++w) c += h[w][d];
-        counts[((int64_t)seg * RS_RADIX + d) * nblk + blk] = c;
+        counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] = c;
     }
     if (FIRST && mom_part != nullptr && tid < 4) {
         double t = 0;
         for (int w = 0; w < RS_WAVES; ++w) t += wsum[w][tid];
-        mom_part[((int64_t)seg * nblk + blk) * 4 + tid] = t;
+        mom_part[(T.tile0 + T.blk) * 4 + tid] = t;
     }
     if (do_hist)
         for (int i = tid; i < ha.cells; i += RS_THREADS)
-            if (cell_h[i]) atomicAdd(&ha.hist[(int64_t)seg * ha.cells + i], cell_h[i]);
+            if (cell_h[i]) atomicAdd(&ha.hist[(int64_t)T.seg * ha.cells + i], cell_h[i]);
 }
 
 // ---------------------------------------------------------------------------
-// Scan: exclusive prefix over the digit-major [256][nblk] counts of a segment.
+// Row scan: one wave per (segment, digit).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) rs_scan(uint32_t *__restrict__ counts, int nblk) {
-    __shared__ uint32_t wtot[16];
-    const int seg = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t L = (int64_t)RS_RADIX * nblk;
-    uint32_t *c = counts + (int64_t)seg * L;
-    const int64_t chunk = (L + 1023) / 1024;
-    const int64_t b = tid * chunk, e = (b + chunk < L) ? b + chunk : L;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += c[i];
-    // inclusive scan of s across the block
-    uint32_t v = s;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off);
-        if (lane >= off) v += t;
-    }
-    if (lane == 63) wtot[wave] = v;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t t = wtot[w];
-            wtot[w] = acc;
-            acc += t;
+template <bool VAR>
+__global__ void __launch_bounds__(256) rs_rowscan(uint32_t *__restrict__ counts, uint32_t *__restrict__ totals,
+                                                  SortLayout L) {
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= (int64_t)L.nseg * RS_RADIX) return;
+    const int lane = threadIdx.x & 63;
+    const int s = (int)(row >> 8), d = (int)(row & 255);
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, s, base, n, tile0, nblk, qrow);
+    uint32_t *c = counts + tile0 * RS_RADIX + (int64_t)d * nblk;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nblk; c0 += 64) {
+        const int i = c0 + lane;
+        const uint32_t v = i < nblk ? c[i] : 0u;
+        uint32_t inc = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
         }
+        if (i < nblk) c[i] = carry + inc - v;
+        carry += __shfl(inc, 63);
     }
-    __syncthreads();
-    uint32_t run = v - s + wtot[wave];  // exclusive prefix of this thread's chunk
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t t = c[i];
-        c[i] = run;
-        run += t;
-    }
+    if (lane == 0) totals[(int64_t)s * RS_RADIX + d] = carry;
 }
 
 // ---------------------------------------------------------------------------
-// Scatter: stable rank inside the tile, LDS staging, contiguous writes.
+// Scatter.
 // ---------------------------------------------------------------------------
-template <typename K, bool FIRST, bool LAST>
+template <typename K, int ITEMS, bool FIRST, bool LAST, bool PAYLOAD, bool VAR>
 __global__ void __launch_bounds__(RS_THREADS)
 rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K *__restrict__ keys_out,
-           uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ offsets, int shift, int64_t n,
-           int nblk, uint32_t *__restrict__ rank_out, uint32_t *__restrict__ perm_out,
-           double *__restrict__ xs_out) {
+           uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
+           const uint32_t *__restrict__ totals, int shift, SortLayout L, uint32_t *__restrict__ rank_out,
+           uint32_t *__restrict__ perm_out, double *__restrict__ xs_out) {
     using V = typename KeyTraits<K>::V;
+    constexpr int WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
     __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
     __shared__ uint32_t wbase[RS_WAVES][RS_RADIX];
     __shared__ uint32_t gdelta[RS_RADIX];
     __shared__ uint32_t wtot[RS_WAVES];
-    __shared__ K skeys[RS_TILE];
-    __shared__ uint32_t svals[RS_TILE];
+    __shared__ K stage[TILE];  // keys, then (reused) payload
 
-    const int seg = blockIdx.y, blk = blockIdx.x;
+    const TileRef T = tile_ref<VAR>(L, blockIdx.x);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t seg_base = (int64_t)seg * n;
-    const int64_t tile0 = (int64_t)blk * RS_TILE + wave * RS_WAVE_KEYS;
+    const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (int i = lane; i < RS_RADIX; i += 64) wcnt[wave][i] = 0;
     wave_sync();
 
-    K key[RS_ITEMS];
-    uint32_t val[RS_ITEMS];
-    uint32_t rnk[RS_ITEMS];
+    K key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t rnk[ITEMS];
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        const int64_t idx = tile0 + i * 64 + lane;
-        if (idx < n) {
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        key[i] = 0;
+        val[i] = 0;
+        if (idx < T.n) {
             if constexpr (FIRST) {
-                key[i] = key_of(((const V *)src)[seg_base + idx]);
+                key[i] = key_of(((const V *)src)[T.base + idx]);
                 val[i] = (uint32_t)idx;
             } else {
-                key[i] = ((const K *)src)[seg_base + idx];
-                val[i] = vals_in[seg_base + idx];
+                key[i] = ((const K *)src)[T.base + idx];
+                if constexpr (PAYLOAD) val[i] = vals_in[T.base + idx];
             }
-        } else {
-            key[i] = 0;
-            val[i] = 0;
         }
     }
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        const bool valid = tile0 + i * 64 + lane < n;
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = t0 + i * 64 + lane < T.n;
         const uint32_t d = (uint32_t)(key[i] >> shift) & 0xFFu;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -229,49 +281,65 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
             c[w] = wcnt[w][d];
             tot += c[w];
         }
-        // exclusive scan of tot over the 256 digits
-        uint32_t v = tot;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t t = __shfl_up(v, off);
-            if (lane >= off) v += t;
-        }
-        if (lane == 63) wtot[wave] = v;
-        __syncthreads();
-        uint32_t pre = 0;
-        for (int w = 0; w < wave; ++w) pre += wtot[w];
-        const uint32_t lstart = pre + v - tot;
+        const uint32_t lstart = block_exclusive_256(tot, wtot);
+        const uint32_t dbase = block_exclusive_256(totals[(int64_t)T.seg * RS_RADIX + d], wtot);
         uint32_t acc = lstart;
 #pragma unroll
         for (int w = 0; w < RS_WAVES; ++w) {
             wbase[w][d] = acc;
             acc += c[w];
         }
-        gdelta[d] = offsets[((int64_t)seg * RS_RADIX + d) * nblk + blk] - lstart;
+        gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - lstart;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
-        if (tile0 + i * 64 + lane < n) {
+    for (int i = 0; i < ITEMS; ++i) {
+        if (t0 + i * 64 + lane < T.n) {
             const uint32_t d = (uint32_t)(key[i] >> shift) & 0xFFu;
-            const uint32_t lp = wbase[wave][d] + rnk[i];
-            skeys[lp] = key[i];
-            svals[lp] = val[i];
+            stage[wbase[wave][d] + rnk[i]] = key[i];
         }
     }
     __syncthreads();
-    const int64_t rem = n - (int64_t)blk * RS_TILE;
-    const int tile_n = rem < RS_TILE ? (int)rem : RS_TILE;
-    for (int j = tid; j < tile_n; j += RS_THREADS) {
-        const K k = skeys[j];
-        const uint32_t v = svals[j];
-        const uint32_t gpos = (uint32_t)j + gdelta[(uint32_t)(k >> shift) & 0xFFu];
-        if ((int64_t)gpos >= n || (int64_t)v >= n) continue;  // unreachable for a consistent scan
-        keys_out[seg_base + gpos] = k;
-        if (!LAST || vals_out) vals_out[seg_base + gpos] = v;
-        if (LAST) {
-            if (rank_out) rank_out[seg_base + v] = gpos;
-            if (perm_out) perm_out[seg_base + gpos] = v;
-            if (xs_out) xs_out[seg_base + gpos] = value_of(k);
+    const int64_t rem = T.n - (int64_t)T.blk * TILE;
+    const int tile_n = rem < TILE ? (int)rem : TILE;
+    uint32_t gpos[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int j = tid + r * RS_THREADS;
+        gpos[r] = 0xFFFFFFFFu;
+        if (j < tile_n) {
+            const K k = stage[j];
+            const uint32_t g = (uint32_t)j + gdelta[(uint32_t)(k >> shift) & 0xFFu];
+            if ((int64_t)g < T.n) {  // always true for a consistent scan
+                gpos[r] = g;
+                keys_out[T.base + g] = k;
+                if (LAST && xs_out) xs_out[T.base + g] = value_of(k);
+            }
+        }
+    }
+    if constexpr (PAYLOAD) {
+        __syncthreads();
+        uint32_t *sv = (uint32_t *)stage;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (t0 + i * 64 + lane < T.n) {
+                const uint32_t d = (uint32_t)(key[i] >> shift) & 0xFFu;
+                sv[wbase[wave][d] + rnk[i]] = val[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int j = tid + r * RS_THREADS;
+            if (j < tile_n && gpos[r] != 0xFFFFFFFFu) {
+                const uint32_t v = sv[j];
+                if (!LAST) {
+                    vals_out[T.base + gpos[r]] = v;
+                } else if ((int64_t)v < T.n) {
+                    if (rank_out) rank_out[T.base + v] = gpos[r];
+                    if (perm_out) perm_out[T.base + gpos[r]] = v;
+                }
+            }
         }
     }
 }
@@ -279,11 +347,13 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 // ---------------------------------------------------------------------------
 // Knots (midpoint convention) from the sorted keys; moment totals.
 // ---------------------------------------------------------------------------
-template <typename K>
-__global__ void rs_knots(const K *__restrict__ sorted, int64_t n, int nq, double *__restrict__ q) {
+template <typename K, bool VAR>
+__global__ void rs_knots(const K *__restrict__ sorted, SortLayout L, int nq, double *__restrict__ q) {
 #pragma clang fp contract(off)
-    const int seg = blockIdx.x;
-    const K *s = sorted + (int64_t)seg * n;
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, blockIdx.x, base, n, tile0, nblk, qrow);
+    const K *s = sorted + base;
     for (int j = threadIdx.x; j <= nq; j += blockDim.x) {
         const double t = (double)((int64_t)j * n) / (double)nq - 0.5;
         double v;
@@ -298,17 +368,21 @@ __global__ void rs_knots(const K *__restrict__ sorted, int64_t n, int nq, double
             v = a + f * (b - a);
             v = v < b ? v : b;
         }
-        q[(int64_t)seg * (nq + 1) + j] = v;
+        q[(int64_t)qrow * (nq + 1) + j] = v;
     }
 }
 
-__global__ void rs_moments(const double *__restrict__ part, int nblk, int64_t n, double *__restrict__ mom) {
-    const int seg = blockIdx.x, lane = threadIdx.x;  // one wave
+template <bool VAR>
+__global__ void rs_moments(const double *__restrict__ part, SortLayout L, double *__restrict__ mom) {
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, blockIdx.x, base, n, tile0, nblk, qrow);
+    const int lane = threadIdx.x;  // one wave
     for (int m = 0; m < 4; ++m) {
         double s = 0;
-        for (int b = lane; b < nblk; b += 64) s += part[((int64_t)seg * nblk + b) * 4 + m];
+        for (int b = lane; b < nblk; b += 64) s += part[(tile0 + b) * 4 + m];
         for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) mom[seg * 4 + m] = s / (double)n;
+        if (lane == 0) mom[(int64_t)qrow * 4 + m] = s / (double)n;
     }
 }
 
@@ -322,32 +396,43 @@ __global__ void zero_u32(uint32_t *p, int64_t count) {
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static int rs_nblk(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
+constexpr int RS_ITEMS = 16;
 
-size_t restrict_ws(int64_t n, int k, int precision) {
-    const size_t ks = precision == PR_F32 ? 4 : 8;
-    const size_t nk = (size_t)n * (size_t)k;
-    const size_t nb = (size_t)rs_nblk(n);
-    return align256(nk * ks) * 2 + align256(nk * 4) * 2 + align256(nb * RS_RADIX * k * 4) +
-           align256(nb * k * 4 * 8) + 256;
+int64_t sort_tiles(int64_t n) {
+    const int64_t tile = (int64_t)RS_THREADS * RS_ITEMS;
+    return (n + tile - 1) / tile;
 }
 
-template <typename K>
-static int restrict_impl(const void *x, int64_t n, int k, int nq, const pr_grid *hg, double *q,
-                         uint32_t *rank, uint32_t *perm, double *xs, double *mom, uint32_t *hist,
-                         void *ws, hipStream_t st) {
-    const int nblk = rs_nblk(n);
-    const size_t nk = (size_t)n * (size_t)k;
+size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload) {
+    const size_t ks = precision == PR_F32 ? 4 : 8;
+    size_t b = align256(total_keys * ks) * 2 + align256((size_t)total_tiles * RS_RADIX * 4) +
+               align256((size_t)nseg * RS_RADIX * 4) + align256((size_t)total_tiles * 4 * 8) + 256;
+    if (payload) b += align256(total_keys * 4) * 2;
+    return b;
+}
+
+size_t restrict_ws(int64_t n, int k, int precision) {
+    return sort_ws_bytes((int64_t)n * k, sort_tiles(n) * k, k, precision, true);
+}
+
+template <typename K, bool VAR>
+static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int64_t total_tiles, int nq,
+                     const pr_grid *hg, double *q, uint32_t *rank, uint32_t *perm, double *xs, double *mom,
+                     uint32_t *hist, void *ws, hipStream_t st) {
+    constexpr int ITEMS = RS_ITEMS;
+    const bool payload = rank || perm;
     char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     K *keys[2];
-    uint32_t *vals[2];
-    keys[0] = (K *)p; p += align256(nk * sizeof(K));
-    keys[1] = (K *)p; p += align256(nk * sizeof(K));
-    vals[0] = (uint32_t *)p; p += align256(nk * 4);
-    vals[1] = (uint32_t *)p; p += align256(nk * 4);
-    uint32_t *counts = (uint32_t *)p; p += align256((size_t)nblk * RS_RADIX * k * 4);
-    double *mom_part = (double *)p;
-
+    uint32_t *vals[2] = {nullptr, nullptr};
+    keys[0] = (K *)p; p += align256(total_keys * sizeof(K));
+    keys[1] = (K *)p; p += align256(total_keys * sizeof(K));
+    uint32_t *counts = (uint32_t *)p; p += align256((size_t)total_tiles * RS_RADIX * 4);
+    uint32_t *totals = (uint32_t *)p; p += align256((size_t)L.nseg * RS_RADIX * 4);
+    double *mom_part = (double *)p; p += align256((size_t)total_tiles * 4 * 8);
+    if (payload) {
+        vals[0] = (uint32_t *)p; p += align256(total_keys * 4);
+        vals[1] = (uint32_t *)p;
+    }
     HistArgs ha{hist, 0, 0.0, 0.0};
     size_t cell_lds = 0;
     if (hist) {
@@ -355,46 +440,48 @@ static int restrict_impl(const void *x, int64_t n, int k, int nq, const pr_grid 
         ha.lo = hg->x_lo;
         ha.inv_h = (double)hg->n_cells / (hg->x_hi - hg->x_lo);
         cell_lds = (size_t)hg->n_cells * 4;
-        const int64_t cnt = (int64_t)k * hg->n_cells;
-        hipLaunchKernelGGL(zero_u32, dim3((unsigned)((cnt + 255) / 256 < 1024 ? (cnt + 255) / 256 : 1024)),
-                           dim3(256), 0, st, hist, cnt);
+        const int64_t cnt = (int64_t)L.nseg * hg->n_cells;
+        const int64_t blocks = (cnt + 255) / 256 < 1024 ? (cnt + 255) / 256 : 1024;
+        hipLaunchKernelGGL(zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, hist, cnt);
         PR_LAUNCHED();
     }
     constexpr int P = KeyTraits<K>::passes;
-    const dim3 grid(nblk, k);
+    const dim3 grid((unsigned)total_tiles);
+    const dim3 rows((unsigned)(((int64_t)L.nseg * RS_RADIX + 3) / 4));
     for (int pass = 0; pass < P; ++pass) {
         const int shift = 8 * pass;
         const int in = (pass + 1) & 1, out = pass & 1;  // pass 0 writes buffer 0
-        if (pass == 0) {
-            hipLaunchKernelGGL((rs_count<K, true>), grid, dim3(RS_THREADS), cell_lds, st, x, shift, n, nblk,
+        if (pass == 0)
+            hipLaunchKernelGGL((rs_count<K, ITEMS, true, VAR>), grid, dim3(RS_THREADS), cell_lds, st, x, shift, L,
                                counts, mom ? mom_part : nullptr, ha);
-        } else {
-            hipLaunchKernelGGL((rs_count<K, false>), grid, dim3(RS_THREADS), 0, st, (const void *)keys[in],
-                               shift, n, nblk, counts, nullptr, HistArgs{nullptr, 0, 0.0, 0.0});
-        }
+        else
+            hipLaunchKernelGGL((rs_count<K, ITEMS, false, VAR>), grid, dim3(RS_THREADS), 0, st,
+                               (const void *)keys[in], shift, L, counts, nullptr, HistArgs{nullptr, 0, 0.0, 0.0});
         PR_LAUNCHED();
-        hipLaunchKernelGGL(rs_scan, dim3(k), dim3(1024), 0, st, counts, nblk);
+        hipLaunchKernelGGL((rs_rowscan<VAR>), rows, dim3(256), 0, st, counts, totals, L);
         PR_LAUNCHED();
         const bool last = pass == P - 1;
-        if (pass == 0) {
-            hipLaunchKernelGGL((rs_scatter<K, true, false>), grid, dim3(RS_THREADS), 0, st, x, nullptr,
-                               keys[out], vals[out], counts, shift, n, nblk, nullptr, nullptr, nullptr);
-        } else if (!last) {
-            hipLaunchKernelGGL((rs_scatter<K, false, false>), grid, dim3(RS_THREADS), 0, st,
-                               (const void *)keys[in], vals[in], keys[out], vals[out], counts, shift, n, nblk,
-                               nullptr, nullptr, nullptr);
+#define PR_SCATTER(FIRST, LAST, PAY, SRC, VIN, VOUT)                                                            \
+    hipLaunchKernelGGL((rs_scatter<K, ITEMS, FIRST, LAST, PAY, VAR>), grid, dim3(RS_THREADS), 0, st, SRC, VIN,     \
+                       keys[out], VOUT, (const uint32_t *)counts, (const uint32_t *)totals, shift, L,          \
+                       LAST ? rank : nullptr, LAST ? perm : nullptr, LAST ? xs : nullptr)
+        if (payload) {
+            if (pass == 0) PR_SCATTER(true, false, true, x, nullptr, vals[out]);
+            else if (!last) PR_SCATTER(false, false, true, (const void *)keys[in], vals[in], vals[out]);
+            else PR_SCATTER(false, true, true, (const void *)keys[in], vals[in], nullptr);
         } else {
-            hipLaunchKernelGGL((rs_scatter<K, false, true>), grid, dim3(RS_THREADS), 0, st,
-                               (const void *)keys[in], vals[in], keys[out], (uint32_t *)nullptr, counts, shift,
-                               n, nblk, rank, perm, xs);
+            if (pass == 0) PR_SCATTER(true, false, false, x, nullptr, nullptr);
+            else if (!last) PR_SCATTER(false, false, false, (const void *)keys[in], nullptr, nullptr);
+            else PR_SCATTER(false, true, false, (const void *)keys[in], nullptr, nullptr);
         }
+#undef PR_SCATTER
         PR_LAUNCHED();
     }
     const K *sorted = keys[(P - 1) & 1];
-    hipLaunchKernelGGL((rs_knots<K>), dim3(k), dim3(128), 0, st, sorted, n, nq, q);
+    hipLaunchKernelGGL((rs_knots<K, VAR>), dim3(L.nseg), dim3(128), 0, st, sorted, L, nq, q);
     PR_LAUNCHED();
     if (mom) {
-        hipLaunchKernelGGL(rs_moments, dim3(k), dim3(64), 0, st, mom_part, nblk, n, mom);
+        hipLaunchKernelGGL((rs_moments<VAR>), dim3(L.nseg), dim3(64), 0, st, (const double *)mom_part, L, mom);
         PR_LAUNCHED();
     }
     return PR_OK;
@@ -403,9 +490,20 @@ static int restrict_impl(const void *x, int64_t n, int k, int nq, const pr_grid 
 int restrict_quantiles(const void *x, int precision, int64_t n, int k, int nq, const pr_grid *hg, double *q,
                        uint32_t *rank, uint32_t *perm, double *xs, double *mom, uint32_t *hist, void *ws,
                        hipStream_t st) {
+    SortLayout L{n, (int)sort_tiles(n), k, nullptr, nullptr};
+    const int64_t tiles = (int64_t)L.nblk * k;
     if (precision == PR_F64)
-        return restrict_impl<uint64_t>(x, n, k, nq, hg, q, rank, perm, xs, mom, hist, ws, st);
-    return restrict_impl<uint32_t>(x, n, k, nq, hg, q, rank, perm, xs, mom, hist, ws, st);
+        return sort_impl<uint64_t, false>(x, L, n * k, tiles, nq, hg, q, rank, perm, xs, mom, hist, ws, st);
+    return sort_impl<uint32_t, false>(x, L, n * k, tiles, nq, hg, q, rank, perm, xs, mom, hist, ws, st);
+}
+
+int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t total_keys, int64_t total_tiles,
+                      int nq, double *q, uint32_t *rank, void *ws, hipStream_t st) {
+    if (precision == PR_F64)
+        return sort_impl<uint64_t, true>(x, L, total_keys, total_tiles, nq, nullptr, q, rank, nullptr, nullptr,
+                                         nullptr, nullptr, ws, st);
+    return sort_impl<uint32_t, true>(x, L, total_keys, total_tiles, nq, nullptr, q, rank, nullptr, nullptr, nullptr,
+                                     nullptr, ws, st);
 }
 
 }  // namespace pr

@@ -1,0 +1,154 @@
+"""GPU tests of the batched form: many uneven instances in one persistent
+launch per phase (optionally a hipGraph), against the same kernels launched
+instance by instance (bitwise), against single-instance handles and against
+the oracle's iteration for each instance."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1912_09240_amd as pr
+from oracle import coarse as OC
+from oracle import iterate as OI
+from oracle import particles as OP
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert pr.available(), "libpr.so not built"
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    with torch.cuda.stream(stream):
+        yield torch
+    torch.cuda.synchronize()
+
+
+# (eps, lambda, n, K, T): uneven on purpose, incl. a ragged particle count
+INSTANCES = [(0.05, 1.3, 3000, 4, 0.2), (0.1, 0.7, 1537, 7, 0.3), (0.02, 1.9, 4096, 3, 0.06),
+             (0.08, 1.0, 700, 5, 0.25), (0.03, 0.55, 2049, 6, 0.12)]
+CELLS, NQ = 60, 50
+
+
+def _make(torch, flags=0, inst=INSTANCES, ids=None):
+    sdes, scheds, ns = [], [], []
+    for eps, lam, n, K, T in inst:
+        dt = eps / 20
+        S = int(round(T / dt))
+        sdes.append(pr.Sde(lam=lam, eps=eps, beta=2.0))
+        scheds.append(pr.Schedule(S, K, T / S))
+        ns.append(n)
+    h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=CELLS, n_q=NQ), 7,
+                                    instances=ids, flags=flags)
+    return h
+
+
+def _states(torch, h, inst=INSTANCES):
+    out = []
+    for i, (eps, lam, n, K, T) in enumerate(inst):
+        for t in range(K + 1):
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+            y = torch.empty(n, dtype=torch.float64, device="cuda")
+            q = torch.empty(NQ + 1, dtype=torch.float64, device="cuda")
+            pr.pr_parareal_batch_state(h, i, t, x=x, y=y, q=q)
+            out.append((x, y, q))
+    torch.cuda.synchronize()
+    return [(a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()) for a, b, c in out]
+
+
+def test_draw_instances_matches_oracle(torch_dev):
+    torch = torch_dev
+    _say("draw instances")
+    out = torch.empty((256, 4), dtype=torch.float64, device="cuda")
+    pr.pr_draw_instances(0, 256, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for i in range(256):
+        eps, lam, n, K = OP.instance_params(0, i)
+        assert abs(o[i, 0] - eps) <= 2 * np.spacing(eps) and abs(o[i, 1] - lam) <= 2 * np.spacing(lam)
+        assert 2 ** int(o[i, 2]) == n and int(o[i, 3]) == K
+
+
+def test_launch_modes_bitwise(torch_dev):
+    """Batched launches, the captured graph and instance-by-instance launches
+    give the same bits; the autotuned shape too."""
+    torch = torch_dev
+    _say("batch modes")
+    results = []
+    for mode, flags in ((pr.PR_LAUNCH_PER_INSTANCE, 0), (pr.PR_LAUNCH_BATCHED, 0), (pr.PR_LAUNCH_GRAPH, 0),
+                        (pr.PR_LAUNCH_BATCHED, pr.PR_AUTOTUNE), (pr.PR_LAUNCH_GRAPH, pr.PR_REUSE_COARSE)):
+        h = _make(torch, flags)
+        try:
+            pr.pr_parareal_batch_iterate(h, 3, mode)
+            results.append((flags, _states(torch, h)))
+            if flags & pr.PR_AUTOTUNE:
+                info = pr.pr_parareal_batch_info(h)
+                assert info["block"] in (128, 256) and info["ppt"] in (1, 2, 4)
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+    ref = results[0][1]
+    for flags, st in results[1:4]:
+        for (a, b, c), (a0, b0, c0) in zip(st, ref):
+            assert np.array_equal(a, a0) and np.array_equal(b, b0) and np.array_equal(c, c0)
+    # the reuse variant differs in general but keeps the initial states
+    assert np.array_equal(results[4][1][0][0], ref[0][0])
+
+
+def test_batch_matches_oracle_per_instance(torch_dev):
+    torch = torch_dev
+    _say("batch vs oracle")
+    inst = INSTANCES[:3]
+    h = _make(torch, 0, inst, ids=[11, 3, 40])
+    try:
+        pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_BATCHED)
+        st = _states(torch, h, inst)
+    finally:
+        pr.pr_parareal_batch_destroy(h)
+    k = 0
+    for (eps, lam, n, K, T), iid in zip(inst, [11, 3, 40]):
+        po, _ = OI.micmac_parareal(OP.Sde(lam=lam, eps=eps, beta=2.0), 7, iid, n, T, eps / 20, K, OC.Grid(CELLS), NQ)
+        po.iterate()
+        po.iterate()
+        for t in range(K + 1):
+            x, y, q = st[k]
+            k += 1
+            assert np.abs(q - po.u[t].restricted(NQ)[0]).max() < 1e-10, (iid, t)
+            assert np.abs(x - po.u[t].x).max() < 1e-9, (iid, t)
+            assert np.abs(y - po.u[t].y[0]).max() < 1e-9, (iid, t)
+
+
+def test_batch_exactness(torch_dev):
+    """After max K iterations every instance equals its serial fine run:
+    knot error exactly zero against the GPU's own serial runs."""
+    torch = torch_dev
+    _say("batch exactness")
+    inst = INSTANCES[:3]
+    h = _make(torch, 0, inst)
+    try:
+        pr.pr_parareal_batch_iterate(h, max(K for (_, _, _, K, _) in inst), pr.PR_LAUNCH_GRAPH)
+        st = _states(torch, h, inst)
+    finally:
+        pr.pr_parareal_batch_destroy(h)
+    k = 0
+    for i, (eps, lam, n, K, T) in enumerate(inst):
+        dt = eps / 20
+        S = int(round(T / dt))
+        sde = pr.Sde(lam=lam, eps=eps, beta=2.0)
+        sched = pr.Schedule(S, K, T / S)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        pr.pr_init_ensemble(sde, 7, i, n, x, y)
+        for t in range(K + 1):
+            if t > 0:
+                pr.pr_fine_propagate(sde, sched, 7, i, n, t - 1, 1, x, y)
+            torch.cuda.synchronize()
+            assert np.array_equal(st[k][0], x.cpu().numpy()), (i, t)
+            k += 1
