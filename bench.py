@@ -134,6 +134,100 @@ def adjoint_measure(torch, pr):
                 jacobian=jac.cpu().tolist(), observables=obs.cpu().tolist())
 
 
+BATCH = dict(count=256, T=2.0, beta=2.0, cells=200, nq=100, seed=0)
+
+
+def batched_measure(torch, pr):
+    """Batched form: 256 instances of the 2-D SDE with eps log-uniform in
+    [1e-3, 1e-1], lambda ~ U(0.5, 2), P in {2^12..2^18}, N in {8..64} slices,
+    dt = eps/20, T = 2 (drawn from the seed), coarse grid 200 cells, 100
+    levels.  The same handle runs iterations in the three launch patterns,
+    which produce the same bits (so the same quantile error): per-instance
+    launches, batched launches, and the batched iteration replayed as a
+    hipGraph.  Device time per iteration from HIP events."""
+    b = BATCH
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    with torch.cuda.stream(stream):
+        draw = torch.empty((b["count"], 4), dtype=torch.float64, device="cuda")
+        pr.pr_draw_instances(b["seed"], b["count"], draw)
+        d = draw.cpu().numpy()
+        sdes, scheds, ns = [], [], []
+        for eps, lam, lg, K in d:
+            dt = eps / 20
+            S = int(round(b["T"] / dt))
+            sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=b["beta"]))
+            scheds.append(pr.Schedule(S, int(K), b["T"] / S))
+            ns.append(2 ** int(lg))
+        t0 = time.perf_counter()
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=b["cells"], n_q=b["nq"]), b["seed"],
+                                        flags=pr.PR_AUTOTUNE)
+        t_create = time.perf_counter() - t0
+        try:
+            info = pr.pr_parareal_batch_info(h)
+            pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_GRAPH)  # capture + warm-up
+            ms_graph = pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH, timed=True) / 2
+            ms_batched = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED, timed=True)
+            ms_plain = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_PER_INSTANCE, timed=True)
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+    w = info["particle_steps"]
+    return dict(workload="256 instances of the 2-D SDE, eps log-uniform [1e-3, 1e-1], lambda U(0.5, 2), "
+                         "P in 2^12..2^18, N in 8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels",
+                fine_particle_steps_per_iteration=w, work_units=info["units"],
+                tuned_block=info["block"], tuned_particles_per_thread=info["ppt"],
+                sweep_ms_graph=ms_graph, sweep_ms_batched=ms_batched, sweep_ms_per_instance=ms_plain,
+                particle_steps_per_s_graph=w / (ms_graph / 1e3),
+                particle_steps_per_s_per_instance=w / (ms_plain / 1e3),
+                speedup_vs_per_instance=ms_plain / ms_graph, create_s=t_create,
+                same_quantile_error="the three launch patterns give bitwise identical states (tested)")
+
+
+HIGHDIM = dict(d=32, n=2 ** 20, dt=1e-4, T=5.0, K=32, eps=0.01, beta=2.0, lam=1.0, seed=0)
+
+
+def highdim_measure(torch, pr):
+    """Fast part in R^32 (dY_i = -(1/eps)(Y_i - a_i X) dt + ..., a_i from the
+    seed): one fine sweep of all 32 slices (P = 2^20, 5e4 steps of 1e-4) in
+    FP64 and in FP32 stepping, from the initial ensemble in every slice.
+    FP32 error stated as the knot difference to the FP64 run (the FP64 path
+    matches the oracle per particle to 1e-12)."""
+    h = HIGHDIM
+    n, K, d = h["n"], h["K"], h["d"]
+    S = int(round(h["T"] / h["dt"]))
+    a = torch.empty(d, dtype=torch.float64, device="cuda")
+    pr.pr_draw_coupling(h["seed"], 0, d, a)
+    out = {}
+    knots = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for prec, dtype in ((pr.PR_F64, torch.float64), (pr.PR_F32, torch.float32)):
+        sde = pr.Sde(lam=h["lam"], eps=h["eps"], beta=h["beta"], d=d, a=a, precision=prec)
+        x0 = torch.empty(n, dtype=dtype, device="cuda")
+        y0 = torch.empty((d, n), dtype=dtype, device="cuda")
+        pr.pr_init_ensemble(sde, h["seed"], 0, n, x0, y0)
+        x = x0.repeat(K, 1).contiguous()
+        y = y0.repeat(K, 1, 1).contiguous()
+        del y0
+        ev[0].record()
+        pr.pr_fine_propagate(sde, pr.Schedule(S, K, h["T"] / S), h["seed"], 0, n, 0, K, x, y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / 1e3
+        xs = x[K - 1].to(torch.float64).contiguous()
+        q = torch.empty(101, dtype=torch.float64, device="cuda")
+        ws = torch.empty(pr.pr_restrict_workspace_size(n, 1), dtype=torch.uint8, device="cuda")
+        pr.pr_restrict_quantiles(xs, pr.PR_F64, n, 1, 100, q, ws)
+        knots[prec] = q.cpu().numpy()
+        out["fp64" if prec == pr.PR_F64 else "fp32"] = dict(sweep_s=t, particle_steps_per_s=n * S / t)
+        del x, y, x0
+        torch.cuda.empty_cache()
+    err = knots[pr.PR_F32] - knots[pr.PR_F64]
+    out["fp32_knot_error_vs_fp64"] = dict(max_abs_interior=float(np.abs(err[1:-1]).max()),
+                                          rms=float(np.sqrt(np.mean(err ** 2))))
+    out["workload"] = ("fast part in R^32, a_i ~ U(0.5, 1.5) from the seed, eps = 0.01, P = 2^20, "
+                       "dt = 1e-4, T = 5 in 32 slices, one sweep of all slices")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,6 +313,10 @@ def main():
                serial_fine_s=t_serial, create_s=t_create)
     log("adjoint")
     out["adjoint"] = adjoint_measure(torch, pr)
+    log("batched instances")
+    out["batched"] = batched_measure(torch, pr)
+    log("fast part in R^32")
+    out["high_dim"] = highdim_measure(torch, pr)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

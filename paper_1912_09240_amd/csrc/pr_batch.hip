@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k2m_units(const double *__restrict__ q, c
         r[i] = (i == 0) ? c[1] : (i == g.cells - 1) ? 1.0 - c[g.cells - 1] : c[i + 1] - c[i];
 }
 
-// E rho for 16 rows of one unit per block, one wave per 4 rows.
+// E rho for 4 rows of one unit per block, one wave per row.
 __device__ __forceinline__ double row_dot(const double *row, const double *v, int n, int lane) {
     double acc = 0.0;
     for (int j = lane; j < n; j += 64) acc = fma(row[j], v[j], acc);
@@ -150,13 +150,10 @@ __global__ void __launch_bounds__(256) apply_units(const double *__restrict__ E,
     for (int j = threadIdx.x; j < n; j += blockDim.x) rv[j] = rin[(int64_t)u * n + j];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = blockIdx.x * 16 + wave * 4;
-    for (int rr = 0; rr < 4; ++rr) {
-        const int r = r0 + rr;
-        if (r >= n) break;
-        const double acc = row_dot(Es + (int64_t)r * n, rv, n, lane);
-        if (lane == 0) rout[(int64_t)u * n + r] = acc > 0.0 ? acc : 0.0;
-    }
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= n) return;
+    const double acc = row_dot(Es + (int64_t)r * n, rv, n, lane);
+    if (lane == 0) rout[(int64_t)u * n + r] = acc > 0.0 ? acc : 0.0;
 }
 
 __global__ void __launch_bounds__(256) m2k_units(const double *__restrict__ rho, const CoarseUnit *__restrict__ cu,
@@ -498,7 +495,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
         hipLaunchKernelGGL(k2m_units, dim3(b->total_slices), dim3(256), sizeof(double) * (g.nq + g.cells + 2), st,
                            cin, (const CoarseUnit *)b->cu, b->rho_a, g);
         PR_LAUNCHED();
-        hipLaunchKernelGGL(apply_units, dim3((g.cells + 15) / 16, b->total_slices), dim3(256),
+        hipLaunchKernelGGL(apply_units, dim3((g.cells + 3) / 4, b->total_slices), dim3(256),
                            sizeof(double) * g.cells, st, (const double *)b->E, (const CoarseUnit *)b->cu,
                            (const double *)b->rho_a, b->rho_b, g.cells);
         PR_LAUNCHED();
@@ -532,7 +529,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
             hipLaunchKernelGGL(k2m_units, dim3(K), dim3(256), sizeof(double) * (g.nq + g.cells + 2), st, cin, cu,
                                b->rho_a, g);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(apply_units, dim3((g.cells + 15) / 16, K), dim3(256), sizeof(double) * g.cells, st,
+            hipLaunchKernelGGL(apply_units, dim3((g.cells + 3) / 4, K), dim3(256), sizeof(double) * g.cells, st,
                                (const double *)b->E, cu, (const double *)b->rho_a, b->rho_b, g.cells);
             PR_LAUNCHED();
             hipLaunchKernelGGL(m2k_units, dim3(K), dim3(256), sizeof(double) * (2 * g.cells + 1), st,

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) knots_to_masses(const double *__restrict_
     }
 }
 
-// rho_out[s] = max(E_{id(s)} rho_in[s], 0).  One wave per 4 rows.
+// rho_out[s] = max(E_{id(s)} rho_in[s], 0).  One wave per row.
 __global__ void __launch_bounds__(256) apply_expm(const double *__restrict__ E, const int *__restrict__ tau_id,
                                                   int slice_first, const double *__restrict__ rin,
                                                   double *__restrict__ rout, int n) {
@@ -109,17 +109,13 @@ __global__ void __launch_bounds__(256) apply_expm(const double *__restrict__ E, 
     for (int j = threadIdx.x; j < n; j += blockDim.x) rv[j] = rin[(int64_t)s * n + j];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r0 = blockIdx.x * 16 + wave * 4;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int r = r0 + rr;
-        if (r >= n) break;
-        const double *row = Es + (int64_t)r * n;
-        double acc = 0.0;
-        for (int j = lane; j < n; j += 64) acc = fma(row[j], rv[j], acc);
-        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) rout[(int64_t)s * n + r] = acc > 0.0 ? acc : 0.0;
-    }
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= n) return;
+    const double *row = Es + (int64_t)r * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc = fma(row[j], rv[j], acc);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) rout[(int64_t)s * n + r] = acc > 0.0 ? acc : 0.0;
 }
 
 __global__ void __launch_bounds__(256) masses_to_knots(const double *__restrict__ rho, double *__restrict__ q,
@@ -334,7 +330,7 @@ int coarse_step(const Coarse *c, int first, int count, const double *q_in, int i
     double *ra = c->rho_a, *rb = rho_out ? rho_out : c->rho_b;
     hipLaunchKernelGGL(knots_to_masses, dim3(count), dim3(256), lds_knots_to_masses(g), st, q_in, in_stride, ra, g);
     PR_LAUNCHED();
-    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 15) / 16, count), dim3(256), sizeof(double) * g.cells, st,
+    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 3) / 4, count), dim3(256), sizeof(double) * g.cells, st,
                        (const double *)c->E, (const int *)c->tau_id, first, (const double *)ra, rb, g.cells);
     PR_LAUNCHED();
     hipLaunchKernelGGL(masses_to_knots, dim3(count), dim3(256), lds_masses_to_knots(g), st, (const double *)rb,
@@ -349,7 +345,7 @@ int coarse_jump(const Coarse *c, int n, const double *q_cur, const double *qf, c
     const GridDev &g = c->g;
     hipLaunchKernelGGL(knots_to_masses, dim3(1), dim3(256), lds_knots_to_masses(g), st, q_cur, 0, c->rho_a, g);
     PR_LAUNCHED();
-    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 15) / 16, 1), dim3(256), sizeof(double) * g.cells, st,
+    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 3) / 4, 1), dim3(256), sizeof(double) * g.cells, st,
                        (const double *)c->E, (const int *)c->tau_id, n, (const double *)c->rho_a, c->rho_b, g.cells);
     PR_LAUNCHED();
     hipLaunchKernelGGL(qf_and_jump, dim3(1), dim3(256), lds_qf_jump(g), st, (const double *)c->rho_b, qf, qcs, q_next,

@@ -44,12 +44,38 @@ __device__ inline double cdf_knots(const double *q, int nq, double x) {
 // block; C must hold cells + 1 doubles of LDS.
 __device__ inline void masses_to_knots_block(const double *rho, double *C, const GridDev &g, double *q) {
 #pragma clang fp contract(off)
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        C[0] = 0.0;
-        for (int i = 0; i < g.cells; ++i) {
-            acc = acc + rho[i];
-            C[i + 1] = acc;
+    // C_{i+1} = C_i + rho_i strictly left to right (the same additions as a
+    // serial loop), done by one wave: each lane holds 16 consecutive masses
+    // in registers and the running sum is handed from lane to lane.
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane == 0) C[0] = 0.0;
+        double carry = 0.0;
+        for (int base = 0; base < g.cells; base += 1024) {
+            double v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int idx = base + lane * 16 + i;
+                v[i] = idx < g.cells ? rho[idx] : 0.0;
+            }
+            double mine = 0.0;
+            for (int l = 0; l < 64; ++l) {
+                if (lane == l) {
+                    double acc = carry;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        if (base + lane * 16 + i < g.cells) acc = acc + v[i];
+                        v[i] = acc;
+                    }
+                    mine = acc;
+                }
+                carry = __shfl(mine, l);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int idx = base + lane * 16 + i;
+                if (idx < g.cells) C[idx + 1] = v[i];
+            }
         }
     }
     __syncthreads();

@@ -10,11 +10,11 @@
 //                   ln u = e ln2 + ln m with ln 2 split in an exact high part.
 //   sqrt_pos(x)     square root, x >= 0: hardware reciprocal-sqrt seed and
 //                   Newton-Raphson (Goldschmidt form) steps.
-//   sincos_quarter(t)  sin(pi t / 2), cos(pi t / 2) for t in [0, 4]: quadrant
-//                   k = rint(t), r = t - k in [-1/2, 1/2] exactly, then the
-//                   Taylor series of sin(pi r/2) to r^15 and cos(pi r/2) to
-//                   r^16 (truncation below 7e-17), coefficients rounded from
-//                   70-digit values of (pi/2)^n / n!.
+//   sincos_half_turn(t)  sin(pi t), cos(pi t) for t in [0, 2]: k = rint(t),
+//                   r = t - k in [-1/2, 1/2] exactly, Taylor series of
+//                   sin(pi r) to r^21 and cos(pi r) to r^20 (truncation below
+//                   2e-17), coefficients rounded from 70-digit values of
+//                   pi^n / n!; an odd k negates both results.
 //
 // All three are within a few ulp of the correctly rounded results; the
 // Box-Muller normals they produce match those of a C library to ~1e-15.
@@ -80,10 +80,11 @@ __host__ __device__ __forceinline__ double log_unit(double u) {
     return __builtin_fma(ed, 0.6931471803691238, __builtin_fma(ed, 1.9082149292705877e-10, lnm));
 }
 
-// sqrt x for x >= 0 (0 gives 0).
+// sqrt x for x >= 0 (0 gives 0: the seed is taken at a tiny positive
+// number and every correction then stays exactly 0).
 __host__ __device__ __forceinline__ double sqrt_pos(double x) {
 #pragma clang fp contract(off)
-    const double y = rsq_seed(x > 0.0 ? x : 1.0);
+    const double y = rsq_seed(__builtin_fmax(x, 0x1p-1000));
     double g = x * y;      // ~ sqrt x
     double h = 0.5 * y;    // ~ 1 / (2 sqrt x)
     const double e = __builtin_fma(-g, h, 0.5);
@@ -93,38 +94,41 @@ __host__ __device__ __forceinline__ double sqrt_pos(double x) {
     g = __builtin_fma(d, h, g);
     d = __builtin_fma(-g, g, x);
     g = __builtin_fma(d, h, g);
-    return x > 0.0 ? g : 0.0;
+    return g;
 }
 
-// sin(pi t/2) -> s, cos(pi t/2) -> c, for t in [0, 4].
-__host__ __device__ __forceinline__ void sincos_quarter(double t, double &s, double &c) {
+// sin(pi t) -> s, cos(pi t) -> c, for t in [0, 2].
+__host__ __device__ __forceinline__ void sincos_half_turn(double t, double &s, double &c) {
 #pragma clang fp contract(off)
-    const double k = __builtin_rint(t);
-    const double r = t - k;  // exact
+    const double k = __builtin_rint(t);  // 0, 1 or 2
+    const double r = t - k;             // exact, in [-1/2, 1/2]
     const double r2 = r * r;
-    double ps = -6.688035109811468e-10;
-    ps = __builtin_fma(ps, r2, 5.692172921967927e-08);
-    ps = __builtin_fma(ps, r2, -3.598843235212085e-06);
-    ps = __builtin_fma(ps, r2, 0.00016044118478735983);
-    ps = __builtin_fma(ps, r2, -0.004681754135318688);
-    ps = __builtin_fma(ps, r2, 0.07969262624616705);
-    ps = __builtin_fma(ps, r2, -0.6459640975062463);
-    ps = __builtin_fma(ps, r2, 1.5707963267948966);
-    const double sn = r * ps;
-    double pc = 6.565963114979473e-11;
-    pc = __builtin_fma(pc, r2, -6.386603083791852e-09);
-    pc = __builtin_fma(pc, r2, 4.710874778818172e-07);
-    pc = __builtin_fma(pc, r2, -2.5202042373060607e-05);
-    pc = __builtin_fma(pc, r2, 0.0009192602748394266);
-    pc = __builtin_fma(pc, r2, -0.02086348076335296);
-    pc = __builtin_fma(pc, r2, 0.25366950790104803);
-    pc = __builtin_fma(pc, r2, -1.2337005501361697);
-    const double cs = __builtin_fma(pc, r2, 1.0);
-    const int q = (int)k & 3;
-    const double a = (q & 1) ? cs : sn;  // |sin| part
-    const double b = (q & 1) ? sn : cs;  // |cos| part
-    s = (q & 2) ? -a : a;
-    c = ((q + 1) & 2) ? -b : b;
+    double ps = 5.392664662608129e-10;
+    ps = __builtin_fma(ps, r2, -2.2948428997269873e-08);
+    ps = __builtin_fma(ps, r2, 7.952054001475513e-07);
+    ps = __builtin_fma(ps, r2, -2.1915353447830217e-05);
+    ps = __builtin_fma(ps, r2, 0.00046630280576761255);
+    ps = __builtin_fma(ps, r2, -0.0073704309457143504);
+    ps = __builtin_fma(ps, r2, 0.08214588661112823);
+    ps = __builtin_fma(ps, r2, -0.5992645293207921);
+    ps = __builtin_fma(ps, r2, 2.5501640398773455);
+    ps = __builtin_fma(ps, r2, -5.16771278004997);
+    ps = __builtin_fma(ps, r2, 3.141592653589793);
+    double pc = 3.604730797462501e-09;
+    pc = __builtin_fma(pc, r2, -1.3878952462213771e-07);
+    pc = __builtin_fma(pc, r2, 4.303069587032947e-06);
+    pc = __builtin_fma(pc, r2, -0.0001046381049248457);
+    pc = __builtin_fma(pc, r2, 0.0019295743094039231);
+    pc = __builtin_fma(pc, r2, -0.02580689139001406);
+    pc = __builtin_fma(pc, r2, 0.2353306303588932);
+    pc = __builtin_fma(pc, r2, -1.3352627688545895);
+    pc = __builtin_fma(pc, r2, 4.0587121264167685);
+    pc = __builtin_fma(pc, r2, -4.934802200544679);
+    pc = __builtin_fma(pc, r2, 1.0);
+    // an odd number of half turns negates both
+    const uint64_t flip = (uint64_t)((int)k & 1) << 63;
+    s = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, r * ps) ^ flip);
+    c = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, pc) ^ flip);
 }
 
 }  // namespace pr

@@ -129,15 +129,15 @@ __device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u
 }
 
 // Box-Muller: z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 log u1).
-// The angle 2 pi u2 = (pi/2)(4 u2) is reduced by quadrants of the exact
-// argument 4 u2, so no range reduction by 2 pi is needed.
+// The angle 2 pi u2 = pi (2 u2) is reduced by half turns of the exact
+// argument 2 u2, so no range reduction by 2 pi is needed.
 __device__ __forceinline__ void box_muller(const Block &b, double &z0, double &z1) {
 #pragma clang fp contract(off)
     double u1, u2;
     uniforms53(b, u1, u2);
     const double r = sqrt_pos(-2.0 * log_unit(u1));
     double s, c;
-    sincos_quarter(4.0 * u2, s, c);
+    sincos_half_turn(2.0 * u2, s, c);
     z0 = r * c;
     z1 = r * s;
 }

