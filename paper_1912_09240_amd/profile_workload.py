@@ -1,0 +1,72 @@
+"""Profiling driver: runs one kernel group of the large workload once, so
+that rocprofv3 counter passes cover a handful of dispatches.
+
+    python -m paper_1912_09240_amd.profile_workload fine      # all 64 slices, one launch
+    python -m paper_1912_09240_amd.profile_workload restrict  # sort of 64 x 2^20 keys with ranks
+    python -m paper_1912_09240_amd.profile_workload match     # matching of 64 x 2^20 particles
+    python -m paper_1912_09240_amd.profile_workload copy      # device-to-device copy of 1 GiB
+
+Large workload: lambda = 1, beta = 2, eps = 0.01, P = 2^20, dt = 1e-4, T = 10
+(1e5 steps) in 64 slices, 100 quantile levels; the slice states start from
+the initial ensemble.  Every group is preceded by one untimed run of itself.
+"""
+import sys
+
+import torch
+
+import paper_1912_09240_amd as pr
+
+N, K, S, DT, NQ = 2 ** 20, 64, 100_000, 1e-4, 100
+
+
+def _ensemble():
+    sde = pr.Sde(lam=1.0, eps=0.01, beta=2.0)
+    x0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    y0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, 0, 0, N, x0, y0)
+    return sde, x0.repeat(K, 1).contiguous(), y0.repeat(K, 1).contiguous()
+
+
+def fine():
+    sde, x, y = _ensemble()
+    sched = pr.Schedule(S, K, DT)
+    for _ in range(2):
+        xs, ys = x.clone(), y.clone()
+        pr.pr_fine_propagate(sde, sched, 0, 0, N, 0, K, xs, ys)
+        torch.cuda.synchronize()
+
+
+def restrict():
+    _, x, _ = _ensemble()
+    ws = torch.empty(pr.pr_restrict_workspace_size(N, K), dtype=torch.uint8, device="cuda")
+    q = torch.empty((K, NQ + 1), dtype=torch.float64, device="cuda")
+    rank = torch.empty((K, N), dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        pr.pr_restrict_quantiles(x, pr.PR_F64, N, K, NQ, q, ws, rank=rank)
+        torch.cuda.synchronize()
+
+
+def match():
+    _, x, _ = _ensemble()
+    ws = torch.empty(pr.pr_restrict_workspace_size(N, K), dtype=torch.uint8, device="cuda")
+    q = torch.empty((K, NQ + 1), dtype=torch.float64, device="cuda")
+    rank = torch.empty((K, N), dtype=torch.int32, device="cuda")
+    pr.pr_restrict_quantiles(x, pr.PR_F64, N, K, NQ, q, ws, rank=rank)
+    qt = q + 0.01
+    for _ in range(2):
+        pr.pr_match_quantiles(qt, q, rank, N, K, NQ, x, x)
+        torch.cuda.synchronize()
+
+
+def copy():
+    a = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+
+if __name__ == "__main__":
+    group = sys.argv[1] if len(sys.argv) > 1 else "fine"
+    {"fine": fine, "restrict": restrict, "match": match, "copy": copy}[group]()
+    print(f"profile_workload {group}: done", flush=True)
