@@ -74,7 +74,8 @@ void or_block(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t m,
     or_philox(ctr, key, out);
 }
 
-/* Two 53-bit uniforms from one block: u1 in (0,1], u2 in [0,1). */
+/* Two 53-bit uniforms from one block: u1 in (0,1], u2 in [0,1).  Used for
+ * the coupling coefficients; the normals take their bits as below. */
 static void or_uniforms(const uint32_t w[4], double *u1, double *u2)
 {
     double a = (double)(w[0] >> 5) * 67108864.0 + (double)(w[1] >> 6);
@@ -83,18 +84,37 @@ static void or_uniforms(const uint32_t w[4], double *u1, double *u2)
     *u2 = b * 0x1p-53;
 }
 
-/* Box-Muller transform of one block into two standard normals. */
+/*
+ * Box-Muller transform of one block (w0, w1, w2, w3) into two standard
+ * normals.  Reading: the paper fixes only the law of the increments, so the
+ * bits are laid out for cheap extraction:
+ *   u = (k + 1/2) 2^-52,  k = (w0 >> 12) 2^32 + w1          u in (0, 1)
+ *   t = (i + f) / 128,    i = (w2 >> 4) mod 256,
+ *                         f = ((w2 >> 12) 2^32 + w3) 2^-52   t in [0, 2)
+ *   z0 = sqrt(-2 ln u) cos(pi t),  z1 = sqrt(-2 ln u) sin(pi t).
+ * u is uniform on a grid of 2^52 midpoints, t on a grid of 2^60 points, so
+ * (z0, z1) is the textbook pair of a radius and a uniform angle.
+ */
+void or_box_muller(const uint32_t w[4], double *z0, double *z1)
+{
+    uint64_t k = ((uint64_t)(w[0] >> 12) << 32) | w[1];
+    uint64_t fbits = ((uint64_t)(w[2] >> 12) << 32) | w[3];
+    uint32_t i = (w[2] >> 4) & 255u;
+    double u = ((double)k + 0.5) * 0x1p-52;
+    double t = ((double)i + (double)fbits * 0x1p-52) / 128.0;
+    double r = sqrt(-2.0 * log(u));
+    double ang = M_PI * t;
+    *z0 = r * cos(ang);
+    *z1 = r * sin(ang);
+}
+
+/* Normal pair j of (tag, m, p). */
 void or_normal_pair(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t m,
                     uint32_t p, uint32_t j, double *z0, double *z1)
 {
     uint32_t w[4];
-    double u1, u2;
     or_block(seed, inst, tag, m, p, j, w);
-    or_uniforms(w, &u1, &u2);
-    double r = sqrt(-2.0 * log(u1));
-    double ang = 2.0 * M_PI * u2;
-    *z0 = r * cos(ang);
-    *z1 = r * sin(ang);
+    or_box_muller(w, z0, z1);
 }
 
 /* Normal number `idx` of (tag, m, p): index 2j is z0 of pair j, 2j+1 is z1. */

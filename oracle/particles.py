@@ -36,12 +36,13 @@ def lib():
         L.or_philox.argtypes = [vp, vp, vp]
         L.or_blocks.argtypes = [u64, u32, u32, u32, i64, i64, u32, vp]
         L.or_normals.argtypes = [u64, u32, u32, u32, i64, i64, i32, vp]
+        L.or_box_muller.argtypes = [vp, vp, vp]
         L.or_coupling.argtypes = [u64, u32, i32, vp]
         L.or_instance_params.argtypes = [u64, u32, P(dbl), P(dbl), P(i64), P(i32)]
         L.or_init_ensemble.argtypes = [P(_Sde), vp, u64, u32, i64, vp, vp]
         L.or_em_propagate.argtypes = [P(_Sde), vp, u64, u32, i64, i64, i64, i64, dbl, vp, vp]
         L.or_em_tangent.argtypes = [P(_Sde), u64, u32, i64, i64, dbl, vp, vp, vp, vp]
-        for f in ("or_philox", "or_blocks", "or_normals", "or_coupling", "or_instance_params",
+        for f in ("or_philox", "or_blocks", "or_normals", "or_box_muller", "or_coupling", "or_instance_params",
                   "or_init_ensemble", "or_em_propagate", "or_em_tangent"):
             getattr(L, f).restype = None
         _LIB = L
@@ -86,6 +87,17 @@ def normals(seed, inst, tag, m, p0, n, n_norm):
     out = np.zeros((n, n_norm), dtype=np.float64)
     lib().or_normals(seed, inst, tag, m, p0, n, n_norm, _ptr(out))
     return out
+
+
+def box_muller(words):
+    """Normal pair of each block of words (rows of 4 x u32) -> (z0, z1)."""
+    w = np.ascontiguousarray(np.atleast_2d(words), dtype=np.uint32)
+    z = np.zeros((len(w), 2), dtype=np.float64)
+    L = lib()
+    for k in range(len(w)):
+        L.or_box_muller(w[k].ctypes.data_as(ctypes.c_void_p), z[k].ctypes.data_as(ctypes.c_void_p),
+                        ctypes.c_void_p(z[k].ctypes.data + 8))
+    return z[:, 0], z[:, 1]
 
 
 def coupling(seed, inst, d):

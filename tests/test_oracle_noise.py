@@ -90,10 +90,63 @@ def test_normal_streams_distinct(oracle_lib):
 
 
 def test_normals_extreme_uniforms_are_finite(oracle_lib):
-    """u1 lies in (0, 1], so log(u1) is finite for every block."""
+    """u lies in (0, 1), so log(u) is finite for every block."""
     z = P.normals(5, 3, 0, 0, 0, 200_000, 2)
     assert np.all(np.isfinite(z))
-    assert np.abs(z).max() < 9.0  # sqrt(-2 log 2^-54) = 8.65 bounds |z|
+    assert np.abs(z).max() < 8.6  # sqrt(-2 log 2^-53) = 8.57 bounds |z|
+
+
+def test_box_muller_bit_layout_closed_forms(oracle_lib):
+    """Words chosen so that u and the angle are known in closed form:
+    u = (k + 1/2) 2^-52 from the top 20 bits of w0 and all of w1; the angle
+    pi t with t = (i + f)/128, i from bits 4..11 of w2, f from bits 12..31 of
+    w2 and all of w3."""
+    M = 0xFFFFFFFF
+    r_min_u = np.sqrt(106.0 * np.log(2.0))          # u = 2^-53
+    cases = [
+        # (words, z0, z1)
+        ((0, 0, 0, 0), r_min_u, 0.0),
+        ((0, 0, 64 << 4, 0), 0.0, r_min_u),             # t = 1/2
+        ((0, 0, 128 << 4, 0), -r_min_u, 0.0),           # t = 1
+        ((0, 0, 192 << 4, 0), 0.0, -r_min_u),           # t = 3/2
+        ((0, 0, 0x80000000, 0), r_min_u * np.cos(np.pi / 256), r_min_u * np.sin(np.pi / 256)),  # f = 1/2
+        ((0, 0, 0xF, 0), r_min_u, 0.0),                 # bits 0..3 of w2 are unused
+        ((0x800, 0, 0, 0), r_min_u, 0.0),               # bits 0..11 of w0 are unused
+    ]
+    for w, e0, e1 in cases:
+        z0, z1 = P.box_muller(np.array(w, dtype=np.uint32))
+        assert abs(z0[0] - e0) < 4e-15 and abs(z1[0] - e1) < 4e-15, (w, z0, z1, e0, e1)
+    # u = 1 - 2^-53 (largest): radius sqrt(-2 ln(1 - 2^-53)) = 2^-26 (1 + O(2^-53))
+    z0, _ = P.box_muller(np.array((M, M, 0, 0), dtype=np.uint32))
+    assert abs(z0[0] / 2.0 ** -26 - 1.0) < 1e-12
+    # u = 1/2 + 2^-53 (k = 2^51): radius sqrt(2 ln 2) to first order
+    z0, _ = P.box_muller(np.array((0x80000000, 0, 0, 0), dtype=np.uint32))
+    assert abs(z0[0] - np.sqrt(2.0 * np.log(2.0))) < 1e-15
+    # w1 is the low word of k: k = 1 gives u = 3 * 2^-53
+    z0, _ = P.box_muller(np.array((0, 1, 0, 0), dtype=np.uint32))
+    assert abs(z0[0] - np.sqrt(-2.0 * np.log(3.0 * 2.0 ** -53))) < 1e-14
+    # w3 is the low word of f: f = 2^-52 moves the angle by pi 2^-59
+    _, z1 = P.box_muller(np.array((0, 0, 0, 1), dtype=np.uint32))
+    assert abs(z1[0] - r_min_u * np.pi * 2.0 ** -59) < 1e-30
+
+
+def test_box_muller_angle_cells_uniform(oracle_lib):
+    """The 256 angle cells (bits 4..11 of w2) are equally likely and the
+    radius is independent of the cell (chi-square, alpha = 1e-3)."""
+    n = 256_000
+    b = P.blocks(9, 0, 0, 5, 0, n)
+    cell = (b[:, 2] >> 4) & 255
+    cnt = np.bincount(cell, minlength=256)
+    assert st.chisquare(cnt).pvalue > 1e-3
+    z = P.normals(9, 0, 0, 5, 0, n, 2)
+    ang = np.mod(np.arctan2(z[:, 1], z[:, 0]), 2 * np.pi)
+    # the angle sits inside its cell [i, i+1) pi/128
+    inside = (ang >= cell * np.pi / 128 - 1e-12) & (ang < (cell + 1) * np.pi / 128 + 1e-12)
+    assert inside.all()
+    r2 = z[:, 0] ** 2 + z[:, 1] ** 2
+    # -2 ln u is Exp(1/2): chi-square with 2 degrees of freedom, independent of the cell
+    assert st.kstest(r2, "chi2", args=(2,)).pvalue > 1e-3
+    assert abs(np.corrcoef(r2, cell)[0, 1]) < 5.0 / np.sqrt(n)
 
 
 def test_coupling_and_instance_params(oracle_lib):
