@@ -20,6 +20,7 @@ recorded on the stream it runs on.  The CPU baseline is the plain oracle
 running one iteration of the same workload on a bounded particle sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,17 +34,33 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s (fwd+adjoint) and parareal sweep time vs plain, same tol"
 WORKLOAD = dict(lam=1.0, beta=2.0, eps=0.01, n=2 ** 20, dt=1e-4, T=10.0, K=64, cells=1024, nq=100, seed=0)
 
-# Minimal VALU instructions per FP64 particle-step (d = 1), counted from the
-# operations the method must perform on gfx950: Philox4x32-10 with the
-# particle index as the only lane-varying counter word (16 lane-varying
-# 32x32->64 products + 18 xor), two 53-bit uniforms (10), ln u1 to FP64
-# accuracy (25), sqrt (9), sin/cos of 2 pi u2 by quadrant reduction (24), the
-# two Box-Muller products (2) and the Euler-Maruyama update (9): 113.  The
-# derivation is in the design notes; the figure is frozen so that the
-# fraction moves only with the kernel's speed.
-VALU_OPS_PER_STEP = 113
+# VALU instructions of one FP64 particle-step (d = 1) on gfx950, the
+# instruction stream the method needs with no address arithmetic, spills or
+# loop control on the vector unit: Philox4x32-10 with the particle index as
+# the only lane-varying counter word (15 lane-varying 32x32->64 products and
+# 17 xor: 32), the Box-Muller pair from table lookups in LDS (u from bit
+# fields 2, -2 ln u 13, sqrt 7, sin/cos of the angle 14, two products 2: 38)
+# and the Euler-Maruyama update (10): 80, counted on isolated builds of each
+# part.  The figure is frozen so that the fraction moves only with speed.
+VALU_OPS_PER_STEP = 80
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
+
+# HBM bytes of one launch of the fine kernel (all 64 slices) from two
+# rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
+# + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
+FINE_TRAFFIC_BYTES = (524365 * 2 + 1048576) * 1024
+FINE_SOURCES_SHA256 = "02ec1f73c754ad165a5680dc8419e21ca120ad1fafc14e275f94f381ecab0afb"
+FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
+                "pr_noise_tables.inc"]
+
+
+def fine_sources_sha256():
+    h = hashlib.sha256()
+    for f in FINE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_09240_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -293,8 +310,10 @@ def main():
     fine_s = phases["fine"] / 1e3
     fine_rate = n * S / fine_s
     achieved = VALU_OPS_PER_STEP * fine_rate
+    traffic = FINE_TRAFFIC_BYTES if fine_sources_sha256() == FINE_SOURCES_SHA256 else None
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=VALU_PEAK / 1e12, unit="Tops/s",
-                    frac=achieved / VALU_PEAK, traffic=None,
+                    frac=achieved / VALU_PEAK, traffic=traffic,
+                    traffic_algorithmic=n * K * 32,
                     kernel="fine_kernel<1,double,2> (all 64 slices, one launch)",
                     fine_ms=phases["fine"], fine_particle_steps_per_s=fine_rate,
                     ops_per_particle_step=VALU_OPS_PER_STEP)

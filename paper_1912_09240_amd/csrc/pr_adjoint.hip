@@ -25,10 +25,10 @@ struct AdCoef {
     double c3, c1, lam, dt, rate, sx, sy, beta, eps;
 };
 
-__device__ __forceinline__ void em_step_d1(double &x, double &y, const AdCoef &c, Key key, uint32_t inst,
-                                           uint32_t m, uint32_t p) {
+__device__ __forceinline__ void em_step_d1(double &x, double &y, const AdCoef &c, const NoiseTab &tab, Key key,
+                                           uint32_t inst, uint32_t m, uint32_t p) {
     double z0, z1;
-    box_muller(noise_block(key, inst, 0u, m, p, 0u), z0, z1);
+    box_muller(noise_block(key, inst, 0u, m, p, 0u), tab, z0, z1);
     const double fx = c.c3 * x * x * x + c.c1 * x + c.lam * (x - y);
     const double xn = x - c.dt * fx + c.sx * z0;
     y = y - c.rate * (y - x) + c.sy * z1;
@@ -39,6 +39,8 @@ __device__ __forceinline__ void em_step_d1(double &x, double &y, const AdCoef &c
 __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, double *__restrict__ y, int64_t n,
                                                        int64_t S, int every, double *__restrict__ ckpt, AdCoef c,
                                                        Key key, uint32_t inst) {
+    __shared__ NoiseTab tab;
+    load_noise_tab(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double xv = x[p], yv = y[p];
@@ -47,7 +49,7 @@ __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, d
         ckpt[(cidx * 2) * n + p] = xv;
         ckpt[(cidx * 2 + 1) * n + p] = yv;
         const int64_t m1 = m0 + every < S ? m0 + every : S;
-        for (int64_t m = m0; m < m1; ++m) em_step_d1(xv, yv, c, key, inst, (uint32_t)m, (uint32_t)p);
+        for (int64_t m = m0; m < m1; ++m) em_step_d1(xv, yv, c, tab, key, inst, (uint32_t)m, (uint32_t)p);
     }
     x[p] = xv;
     y[p] = yv;
@@ -58,6 +60,8 @@ __global__ void __launch_bounds__(AD_THREADS)
 adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n, int64_t S,
                const double *__restrict__ seed_x, const double *__restrict__ seed_y, int from_initial,
                double *__restrict__ sub, double *__restrict__ part, AdCoef c, Key key, uint32_t inst) {
+    __shared__ NoiseTab tab;
+    load_noise_tab(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = p < n;
     const int64_t pc = live ? p : 0;
@@ -81,7 +85,7 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
                 sub[(2 * (int64_t)nsub) * n + p] = xv;
                 sub[(2 * (int64_t)nsub + 1) * n + p] = yv;
                 const int64_t me = ms + AD_SUB < m1 ? ms + AD_SUB : m1;
-                for (int64_t m = ms; m < me; ++m) em_step_d1(xv, yv, c, key, inst, (uint32_t)m, (uint32_t)p);
+                for (int64_t m = ms; m < me; ++m) em_step_d1(xv, yv, c, tab, key, inst, (uint32_t)m, (uint32_t)p);
             }
             // level 2: each sub-segment, last first
             for (int j = nsub - 1; j >= 0; --j) {
@@ -93,7 +97,7 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
 #pragma unroll
                 for (int i = 0; i < AD_SUB; ++i) {
                     double a = tx[i], b = ty[i];
-                    if (i < L) em_step_d1(a, b, c, key, inst, (uint32_t)(ms + i), (uint32_t)p);
+                    if (i < L) em_step_d1(a, b, c, tab, key, inst, (uint32_t)(ms + i), (uint32_t)p);
                     tx[i + 1] = a;
                     ty[i + 1] = b;
                 }

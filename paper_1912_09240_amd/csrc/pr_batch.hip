@@ -81,6 +81,8 @@ __global__ void __launch_bounds__(256) fine_batch_kernel(const Unit *__restrict_
                                                          const double *xin, const double *yin, double *xout,
                                                          double *yout, Key key) {
     __shared__ int u_sh;
+    __shared__ NoiseTab tab;
+    load_noise_tab(tab);
     const double a1[1] = {1.0};
     for (;;) {
         if (threadIdx.x == 0) u_sh = (int)atomicAdd(counter, 1u);
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(256) fine_batch_kernel(const Unit *__restrict_
         }
         for (int64_t m = m0; m < m1; ++m) {
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) em_step<1, double>(xv[q], yv[q], a1, I.c, key, I.inst, (uint32_t)m, pp[q]);
+            for (int q = 0; q < PPT; ++q) em_step<1, double>(xv[q], yv[q], a1, I.c, tab, key, I.inst, (uint32_t)m, pp[q]);
         }
 #pragma unroll
         for (int q = 0; q < PPT; ++q)

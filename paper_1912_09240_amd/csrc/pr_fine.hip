@@ -13,6 +13,8 @@ __global__ void __launch_bounds__(256) fine_kernel(const T *xin, const T *yin, T
                                                    int slice_first, int64_t S, int N,
                                                    EmCoef<T> c, const double *__restrict__ a_dev,
                                                    Key key, uint32_t inst) {
+    __shared__ NoiseTab tab;
+    load_noise_tab(tab);
     const int s = blockIdx.y;
     const int sl = slice_first + s;
     const int64_t m0 = slice_begin(S, N, sl);
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(256) fine_kernel(const T *xin, const T *yin, T
     for (int64_t m = m0; m < m1; ++m) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
-            em_step<D, T>(xv[q], yv[q], a, c, key, inst, (uint32_t)m, (uint32_t)(base + (int64_t)q * blockDim.x));
+            em_step<D, T>(xv[q], yv[q], a, c, tab, key, inst, (uint32_t)m, (uint32_t)(base + (int64_t)q * blockDim.x));
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -53,12 +55,14 @@ template <int D, typename T>
 __global__ void __launch_bounds__(256) init_kernel(T *__restrict__ x, T *__restrict__ y, int64_t n,
                                                    const double *__restrict__ a_dev, double sd_y,
                                                    Key key, uint32_t inst) {
+    __shared__ NoiseTab tab;
+    load_noise_tab(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     constexpr int NP = (D + 2) / 2;
     double z[2 * NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) box_muller(noise_block(key, inst, 1u, 0u, (uint32_t)p, (uint32_t)j), z[2 * j], z[2 * j + 1]);
+    for (int j = 0; j < NP; ++j) box_muller(noise_block(key, inst, 1u, 0u, (uint32_t)p, (uint32_t)j), tab, z[2 * j], z[2 * j + 1]);
     const double x0 = 0.5 * z[0];
     x[p] = (T)x0;
 #pragma unroll

@@ -12,25 +12,25 @@ namespace pr {
 // Parameters of the scheme, precomputed on the host.
 template <typename T>
 struct EmCoef {
-    T c3, c1, lam;  // drift of X: c3 x^3 + c1 x + lam (x - ybar)
-    T dt;           // fine step
-    T rate;         // dt / eps
-    T sx;           // sqrt(2 dt / beta)
-    T sy;           // sqrt(2 dt / (beta eps))
+    T a3, a1, al;  // -dt times the drift coefficients of X: c3 x^3 + c1 x + lam (x - ybar)
+    T rate;        // dt / eps
+    T sx;          // sqrt(2 dt / beta)
+    T sy;          // sqrt(2 dt / (beta eps))
 };
 
 template <typename T>
-__device__ __forceinline__ void normal_pair(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                            uint32_t p, uint32_t j, T &z0, T &z1);
+__device__ __forceinline__ void normal_pair(const NoiseTab &tab, Key key, uint32_t inst, uint32_t tag,
+                                            uint32_t m, uint32_t p, uint32_t j, T &z0, T &z1);
 
 template <>
-__device__ __forceinline__ void normal_pair<double>(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                                    uint32_t p, uint32_t j, double &z0, double &z1) {
-    box_muller(noise_block(key, inst, tag, m, p, j), z0, z1);
+__device__ __forceinline__ void normal_pair<double>(const NoiseTab &tab, Key key, uint32_t inst, uint32_t tag,
+                                                    uint32_t m, uint32_t p, uint32_t j, double &z0,
+                                                    double &z1) {
+    box_muller(noise_block(key, inst, tag, m, p, j), tab, z0, z1);
 }
 template <>
-__device__ __forceinline__ void normal_pair<float>(Key key, uint32_t inst, uint32_t tag, uint32_t m,
-                                                   uint32_t p, uint32_t j, float &z0, float &z1) {
+__device__ __forceinline__ void normal_pair<float>(const NoiseTab &, Key key, uint32_t inst, uint32_t tag,
+                                                   uint32_t m, uint32_t p, uint32_t j, float &z0, float &z1) {
     box_muller_f32(noise_block(key, inst, tag, m, p, j), z0, z1);
 }
 
@@ -40,12 +40,12 @@ __device__ __forceinline__ float fmaf_t(float a, float b, float c) { return __bu
 // One Euler-Maruyama step of one particle, drift at the old state.
 template <int D, typename T>
 __device__ __forceinline__ void em_step(T &x, T (&y)[D], const T (&a)[D], const EmCoef<T> &c,
-                                        Key key, uint32_t inst, uint32_t m, uint32_t p) {
+                                        const NoiseTab &tab, Key key, uint32_t inst, uint32_t m, uint32_t p) {
 #pragma clang fp contract(off)
     constexpr int NP = (D + 2) / 2;  // pairs of normals for 1 + D components
     T z[2 * NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) normal_pair<T>(key, inst, 0u, m, p, (uint32_t)j, z[2 * j], z[2 * j + 1]);
+    for (int j = 0; j < NP; ++j) normal_pair<T>(tab, key, inst, 0u, m, p, (uint32_t)j, z[2 * j], z[2 * j + 1]);
     T ybar;
     if constexpr (D == 1) {
         ybar = y[0];
@@ -56,14 +56,20 @@ __device__ __forceinline__ void em_step(T &x, T (&y)[D], const T (&a)[D], const 
         ybar = s / (T)D;
     }
     // fused multiply-adds written out, everything else unfused, so that every
-    // kernel that inlines this step produces the same bits
+    // kernel that inlines this step produces the same bits:
+    //   x' = x - dt lam (x - ybar) - dt c1 x - dt c3 x^3 + sx z0
+    const T d = x - ybar;
     const T x2 = x * x;
-    const T fx = fmaf_t(c.c3 * x2, x, fmaf_t(c.c1, x, c.lam * (x - ybar)));
-    const T xn = fmaf_t(c.sx, z[0], fmaf_t(-c.dt, fx, x));
+    T t = fmaf_t(c.al, d, x);
+    t = fmaf_t(c.a1, x, t);
+    t = fmaf_t(c.a3 * x2, x, t);
+    const T xn = fmaf_t(c.sx, z[0], t);
+    if constexpr (D == 1) {
+        // y' = y + (dt/eps) (x - y) + sy z1
+        y[0] = fmaf_t(c.sy, z[1], fmaf_t(c.rate, d, y[0]));
+    } else {
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const T gy = (D == 1) ? (y[i] - x) : (y[i] - a[i] * x);
-        y[i] = fmaf_t(c.sy, z[i + 1], fmaf_t(-c.rate, gy, y[i]));
+        for (int i = 0; i < D; ++i) y[i] = fmaf_t(c.sy, z[i + 1], fmaf_t(-c.rate, y[i] - a[i] * x, y[i]));
     }
     x = xn;
 }
@@ -71,10 +77,9 @@ __device__ __forceinline__ void em_step(T &x, T (&y)[D], const T (&a)[D], const 
 template <typename T>
 inline EmCoef<T> make_coef(const pr_sde *s, double dt) {
     EmCoef<T> c;
-    c.c3 = (T)s->c3;
-    c.c1 = (T)s->c1;
-    c.lam = (T)s->lambda;
-    c.dt = (T)dt;
+    c.a3 = (T)(-dt * s->c3);
+    c.a1 = (T)(-dt * s->c1);
+    c.al = (T)(-dt * s->lambda);
     c.rate = (T)(dt / s->eps);
     c.sx = (T)std::sqrt(2.0 * dt / s->beta);
     c.sy = (T)std::sqrt(2.0 * dt / (s->beta * s->eps));

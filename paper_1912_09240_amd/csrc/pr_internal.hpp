@@ -11,6 +11,7 @@
 
 #include "pr.h"
 #include "pr_fastmath.hpp"
+#include "pr_normal.hpp"
 
 namespace pr {
 
@@ -128,27 +129,20 @@ __device__ __forceinline__ void uniforms53(const Block &b, double &u1, double &u
     u2 = c * 0x1p-53;
 }
 
-// Box-Muller: z0 = r cos(2 pi u2), z1 = r sin(2 pi u2), r = sqrt(-2 log u1).
-// The angle 2 pi u2 = pi (2 u2) is reduced by half turns of the exact
-// argument 2 u2, so no range reduction by 2 pi is needed.
-__device__ __forceinline__ void box_muller(const Block &b, double &z0, double &z1) {
-#pragma clang fp contract(off)
-    double u1, u2;
-    uniforms53(b, u1, u2);
-    const double r = sqrt_pos(-2.0 * log_unit(u1));
-    double s, c;
-    sincos_half_turn(2.0 * u2, s, c);
-    z0 = r * c;
-    z1 = r * s;
+// Box-Muller pair of one block, FP64 (bit layout and elementary functions in
+// pr_normal.hpp; the tables must be in LDS, see load_noise_tab).
+__device__ __forceinline__ void box_muller(const Block &b, const NoiseTab &tab, double &z0, double &z1) {
+    normal_pair_of_words(b.w0, b.w1, b.w2, b.w3, tab, z0, z1);
 }
 
-// FP32 variant: 24-bit uniforms u1 in (0, 1], u2 in [0, 1).
+// FP32 variant with the same bits at single precision: u from the top 24
+// bits of w0, the angle from bits 4..31 of w2 (no tables).
 __device__ __forceinline__ void box_muller_f32(const Block &b, float &z0, float &z1) {
     const float u1 = ((float)(b.w0 >> 8) + 0.5f) * 0x1p-24f;
-    const float u2 = (float)(b.w2 >> 8) * 0x1p-24f;
+    const float t = ((float)((b.w2 >> 4) & 255u) + (float)(b.w2 >> 12) * 0x1p-20f) * 0x1p-7f;
     const float r = sqrtf(-2.0f * logf(u1));
     float s, c;
-    sincospif(2.0f * u2, &s, &c);
+    sincospif(t, &s, &c);
     z0 = r * c;
     z1 = r * s;
 }

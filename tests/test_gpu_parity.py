@@ -61,8 +61,15 @@ def test_init_ensemble(torch_dev, d, n):
     pr.pr_init_ensemble(s, 7, 3, n, x, y)
     _sync(torch)
     xo, yo = OP.init_ensemble(OP.Sde(beta=2.0, d=d, a=a_np), 7, 3, n)
-    assert np.abs(x.cpu().numpy() - xo).max() < 1e-14
-    assert np.abs(y.cpu().numpy() - yo).max() < 1e-14
+    xg, yg = x.cpu().numpy(), y.cpu().numpy()
+    if d == 1:
+        # x = z0 / 2, y = x + z1 / sqrt(2): the normals themselves, to the
+        # oracle's rounding of the angle (~1e-15 of the radius r)
+        r = np.hypot(2 * xo, (yo[0] - xo) * np.sqrt(2.0))
+        assert np.all(np.abs(xg - xo) <= 0.5e-15 * (1 + r))
+        assert np.all(np.abs(yg[0] - yo[0]) <= 2e-15 * (1 + r))
+    assert np.abs(xg - xo).max() < 1e-14
+    assert np.abs(yg - yo).max() < 1e-14
 
 
 @pytest.mark.parametrize("d,n,S,K,dt,eps", [(1, 4_099, 300, 3, 1e-3, 0.1), (1, 10_000, 1000, 10, 1e-3, 0.1),
