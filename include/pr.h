@@ -115,15 +115,18 @@ int pr_version(void);
 /*
  * Noise.  Every normal number comes from Philox4x32-10 (Salmon et al., SC'11)
  * with key (lo32(seed), hi32(seed)) and counter (m, p, tag<<16 | j, instance),
- * m the global step, p the particle, j the pair index; the two 53-bit uniforms
- * of a block give two normals by Box-Muller; normal 2j and 2j+1 of a particle
- * use pair j.  Tags: 0 EM increments, 1 initial ensemble, 2 coefficients a_i,
+ * m the global step, p the particle, j the pair index.  A block (w0..w3)
+ * gives two normals by Box-Muller from u = (k + 1/2) 2^-52 with
+ * k = (w0 >> 12) 2^32 + w1 and the angle pi t, t = (i + f)/128 with
+ * i = (w2 >> 4) mod 256 and f = ((w2 >> 12) 2^32 + w3) 2^-52; normal 2j and
+ * 2j+1 of a particle use pair j.  Tags: 0 EM increments, 1 initial ensemble, 2 coefficients a_i,
  * 3 batched-instance parameters.  Noise therefore depends only on
  * (seed, instance, step, particle): a slice run twice uses the same numbers
  * (Sec. 6) and any subset of particles can be recomputed.
  */
 
-/* a[i] = 0.5 + u (u uniform of block (tag 2, m = 0, p = i)), i < d.
+/* a[i] = 0.5 + u, u = ((w2 >> 5) 2^26 + (w3 >> 6)) 2^-53 of block
+ * (tag 2, m = 0, p = i), i < d.
  * a: device, d doubles. */
 int pr_draw_coupling(uint64_t seed, uint32_t instance, int d, double *a, void *stream);
 
