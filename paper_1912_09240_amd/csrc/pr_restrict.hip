@@ -18,6 +18,8 @@
 // and generates the particle index as payload; the last pass writes the
 // outputs asked for (rank by scatter, perm and sorted values in order).  A
 // sort that only needs knots carries no payload.
+#include <type_traits>
+
 #include "pr_internal.hpp"
 
 namespace pr {
@@ -62,6 +64,19 @@ struct TileRef {
     int seg, blk, nblk;
     int64_t base, n, tile0;
 };
+
+// Tile processed by block b of nb.  Blocks are handed to the 8 XCDs round
+// robin (block b runs on XCD b mod 8) and every XCD has its own L2, so each
+// XCD takes one contiguous range of tiles: neighbouring tiles share cache
+// lines of the per-tile count columns and of the digit runs they write, and
+// those lines then fill up in one L2 instead of being written partially from
+// several.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    constexpr int64_t X = 8;
+    const int64_t q = nb / X, r = nb % X;
+    const int64_t x = b % X, i = b / X;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
 
 template <bool VAR>
 __device__ __forceinline__ TileRef tile_ref(const SortLayout &L, int64_t t) {
@@ -113,25 +128,35 @@ rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__rest
          double *__restrict__ mom_part, HistArgs ha) {
     using V = typename KeyTraits<K>::V;
     constexpr int WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
-    __shared__ uint32_t h[RS_WAVES][RS_RADIX];
+    // two copies of every wave's histogram (even and odd lanes) halve the
+    // same-address serialisation of the LDS atomics when few digits occur
+    __shared__ uint32_t h[RS_WAVES][2][RS_RADIX];
     __shared__ double wsum[RS_WAVES][4];
     extern __shared__ uint32_t cell_h[];
-    const TileRef T = tile_ref<VAR>(L, blockIdx.x);
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < RS_WAVES * RS_RADIX; i += RS_THREADS) (&h[0][0])[i] = 0;
+    for (int i = tid; i < RS_WAVES * 2 * RS_RADIX; i += RS_THREADS) (&h[0][0][0])[i] = 0;
     const bool do_hist = FIRST && ha.hist != nullptr;
     if (do_hist)
         for (int i = tid; i < ha.cells; i += RS_THREADS) cell_h[i] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
+    // all loads of the tile first, so that they are in flight together
+    using In = typename std::conditional<FIRST, V, K>::type;
+    In in[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        in[i] = idx < T.n ? ((const In *)src)[T.base + idx] : (In)0;
+    }
     double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = t0 + i * 64 + lane;
         if (idx < T.n) {
             K key;
             if constexpr (FIRST) {
-                const V v = ((const V *)src)[T.base + idx];
+                const V v = in[i];
                 key = key_of(v);
                 const double xv = (double)v;
                 const double x2 = xv * xv;
@@ -145,9 +170,9 @@ rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__rest
                     atomicAdd(&cell_h[(int)c], 1u);
                 }
             } else {
-                key = ((const K *)src)[T.base + idx];
+                key = in[i];
             }
-            atomicAdd(&h[wave][(uint32_t)(key >> shift) & 0xFFu], 1u);
+            atomicAdd(&h[wave][lane & 1][(uint32_t)(key >> shift) & 0xFFu], 1u);
         }
     }
     if (FIRST && mom_part != nullptr) {
@@ -169,7 +194,7 @@ rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__rest
         const int d = tid;  // RS_THREADS == RS_RADIX
         uint32_t c = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) c += h[w][d];
+        for (int w = 0; w < RS_WAVES; ++w) c += h[w][0][d] + h[w][1][d];
         counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] = c;
     }
     if (FIRST && mom_part != nullptr && tid < 4) {
@@ -228,7 +253,7 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
     __shared__ uint32_t wtot[RS_WAVES];
     __shared__ K stage[TILE];  // keys, then (reused) payload
 
-    const TileRef T = tile_ref<VAR>(L, blockIdx.x);
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
