@@ -89,13 +89,16 @@ def match_quantiles(x_prior, rank, q_target, q_prior):
 #   fine(n, u)       : fine propagator over slice n       (micro state)
 #   coarse(n, rho)   : coarse propagator over slice n     (macro state)
 #   restrict(u)      : micro -> macro
-#   match(rho, u*)   : macro -> micro given a prior
+#   match(rho, u*)   : macro -> micro given a prior (with timed_match,
+#                      match(rho, u*, n) for the time point n it produces)
 #   jump(c, f, cs)   : the iterator J
 # --------------------------------------------------------------------------
 class Parareal:
-    def __init__(self, u0, n_slices, fine, coarse, restrict, match, jump, reuse_coarse=False):
+    def __init__(self, u0, n_slices, fine, coarse, restrict, match, jump, reuse_coarse=False,
+                 timed_match=False):
         self.K = n_slices
-        self.fine, self.coarse, self.restrict, self.match, self.jump = fine, coarse, restrict, match, jump
+        self.fine, self.coarse, self.restrict, self.jump = fine, coarse, restrict, jump
+        self.match = match if timed_match else (lambda rho, prior, n: match(rho, prior))
         self.reuse = reuse_coarse
         self.k = 0
         # zeroth iteration: a coarse pass from R(u0), matched against u0
@@ -104,7 +107,7 @@ class Parareal:
         for n in range(self.K):
             rho.append(coarse(n, rho[n]))
         self.rho = rho
-        self.u = [u0] + [match(rho[n], u0) for n in range(1, self.K + 1)]
+        self.u = [u0] + [self.match(rho[n], u0, n) for n in range(1, self.K + 1)]
 
     def iterate(self):
         K = self.K
@@ -120,7 +123,7 @@ class Parareal:
         for n in range(K):
             rho_new.append(self.jump(self.coarse(n, rho_new[n]), rho_f[n + 1], rho_cs[n + 1]))
         # matching with the fine results as priors
-        self.u = [self.u[0]] + [self.match(rho_new[n + 1], ubar[n + 1]) for n in range(K)]
+        self.u = [self.u[0]] + [self.match(rho_new[n + 1], ubar[n + 1], n + 1) for n in range(K)]
         self.rho = rho_new
         self.k += 1
 
