@@ -300,6 +300,85 @@ int pr_fine_adjoint(const pr_sde *sde, const pr_schedule *sched, uint64_t seed, 
                     const double *seed_y, int n_seed, int from_initial, double *grad, void *ws,
                     size_t ws_bytes, void *stream);
 
+/*
+ * Histogram-state micro-macro parareal (Sec. 4, Sec. 5): the macroscopic
+ * state is the vector of cell masses rho[I] of the slow variable on the grid
+ * (eq. (integral)); the ensembles are FP64 with optional particle weights.
+ * Cell i is [x_i, x_{i+1}) with index floor((x - x_lo) I/(x_hi - x_lo))
+ * clamped to the grid; at most 1024 cells.
+ */
+enum {                  /* iterators J(rho_c^{n+1}, rho_f^*, rho_c^*), Sec. 4    */
+    PR_J_ADD = 0,       /* rho_f + (rho_c^{n+1} - rho_c^*); negative cells set to 0
+                           and then the result scaled to the mass of rho_f      */
+    PR_J_MULT = 1,      /* rho_f (rho_c^{n+1} / rho_c^*) where rho_c^* > 0, else 0,
+                           scaled to the mass of rho_f                           */
+    PR_J_ROT = 2,       /* rotation of sqrt(rho_f) in the plane of sqrt(rho_c^*)
+                           and sqrt(rho_c^{n+1}) (Sec. 4.3, closed form)         */
+    PR_J_QUANTILE = 3   /* quantile add/subtract on the union of the three cdfs'
+                           edge levels, pool-adjacent-violators, back to masses  */
+};
+enum {                       /* matchings M(rho, prior), Sec. 5                   */
+    PR_M_MARGINAL = 0,       /* X = q_rho(cbar(Xbar)) on piecewise-linear cdfs;
+                                fast variables and weights unchanged            */
+    PR_M_REWEIGHT = 1,       /* W = Wbar rho'_i / rhobar_i, rho' = rho with the
+                                mass of cells without prior particles handed to
+                                the nearest supported cells                    */
+    PR_M_RESAMPLE = 2,       /* reweighting, then stratified resampling with
+                                u_j = (j + U[0,1))/P drawn from the seed         */
+    PR_M_RESAMPLE_DET = 3    /* the same with u_j = (j + 1/2)/P                   */
+};
+
+/* rho[s][I] (device) = weighted histogram of x[s][n] (device), s < k; w[s][n]
+ * the weights or NULL for equal weights RN(1/n).  Each mass is the exact sum
+ * of its cell's weights rounded once (weights in [2^-60, 2^15) or 0).
+ * Workspace: pr_hist_workspace_size(k, n_cells) bytes. */
+size_t pr_hist_workspace_size(int k, int n_cells);
+int pr_hist_restrict(const double *x, const double *w, int64_t n, int k, const pr_grid *grid, double *rho,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* rho_out[s] = J(rho_c[s], rho_f[s], rho_cs[s]) for k independent triples of
+ * histograms [k][I] (device); rho_out must not alias an input.  The quantile
+ * iterator needs pr_hist_jump_workspace_size(k, n_cells) bytes of workspace
+ * (the others accept ws = NULL).  Sums over the cells run left to right. */
+size_t pr_hist_jump_workspace_size(int k, int n_cells);
+int pr_hist_jump(int kind, const double *rho_c, const double *rho_f, const double *rho_cs, int k,
+                 const pr_grid *grid, double *rho_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Matching of k ensembles of n particles.  rho_t [k][I] targets, rho_p [k][I]
+ * the histograms of the priors (pr_hist_restrict of x, w); prior x [n] or
+ * [k][n] (prior_stride 0 or n), y [D][n] or [k][D][n], w likewise or NULL
+ * for equal weights.  Outputs [k][n], [k][D][n], [k][n]:
+ *   MARGINAL writes x_out only (may equal x);
+ *   REWEIGHT writes w_out only (may equal w);
+ *   RESAMPLE(_DET) writes x_out, y_out, w_out (no aliasing with the prior);
+ *     slot j of ensemble s takes the prior particle p whose cumulative
+ *     fixed-point weight interval holds U_j (Philox block (tag 4, m = 0,
+ *     p = j, pair = t_first + s, instance) for the random variant).
+ * Workspace: pr_hist_match_workspace_size(n, k, n_cells) bytes. */
+size_t pr_hist_match_workspace_size(int64_t n, int k, int n_cells);
+int pr_hist_match(int kind, const double *rho_t, const double *rho_p, int64_t n, int k, int d,
+                  const pr_grid *grid, const double *x, const double *y, const double *w, int64_t prior_stride,
+                  double *x_out, double *y_out, double *w_out, uint64_t seed, uint32_t instance, int t_first,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Histogram-state parareal driver (FP64).  create runs the zeroth iteration
+ * (rho^0 = R(X0), rho^{n+1} = C_n(rho^n), X^n = M(rho^n; X0)); iterate runs
+ * generic iterations: fine propagation of every slice, restriction of the
+ * fine results and of the current states, coarse propagation, the serial
+ * chain of coarse step and iterator, matching against the fine results.
+ * Flags: PR_REUSE_COARSE (C of the previous macro states), PR_PROFILE.
+ * rho_ref [K+1][I] (device) makes iterate compute the L2 error of the new
+ * states' histograms per time point; err_out (host) receives [n_iter][2]:
+ * the error at n = N and the maximum over n. */
+int pr_parareal_hist_create(const pr_sde *sde, const pr_schedule *sched, const pr_grid *grid, uint64_t seed,
+                            uint32_t instance, int64_t n, int iterator, int matching, int flags, void *stream,
+                            void **h);
+int pr_parareal_hist_iterate(void *h, int n_iter, const double *rho_ref, double *err_out, void *stream);
+int pr_parareal_hist_state(void *h, int t, double *x, double *y, double *w, double *rho, void *stream);
+int pr_parareal_hist_iteration(const void *h);
+int pr_parareal_hist_profile(const void *h, double *ms_out, int *iterations);
+int pr_parareal_hist_destroy(void *h);
+
 #ifdef __cplusplus
 }
 #endif

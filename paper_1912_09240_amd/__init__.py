@@ -21,6 +21,10 @@ __all__ = [
     "pr_adjoint_workspace_size", "pr_fine_adjoint", "pr_draw_instances", "pr_parareal_batch_create",
     "pr_parareal_batch_iterate", "pr_parareal_batch_state", "pr_parareal_batch_info", "pr_parareal_batch_destroy",
     "PR_AUTOTUNE", "PR_LAUNCH_BATCHED", "PR_LAUNCH_GRAPH", "PR_LAUNCH_PER_INSTANCE",
+    "PR_J_ADD", "PR_J_MULT", "PR_J_ROT", "PR_J_QUANTILE", "PR_M_MARGINAL", "PR_M_REWEIGHT", "PR_M_RESAMPLE",
+    "PR_M_RESAMPLE_DET", "pr_hist_workspace_size", "pr_hist_restrict", "pr_hist_jump_workspace_size", "pr_hist_jump",
+    "pr_hist_match_workspace_size", "pr_hist_match", "pr_parareal_hist_create", "pr_parareal_hist_iterate",
+    "pr_parareal_hist_state", "pr_parareal_hist_iteration", "pr_parareal_hist_profile", "pr_parareal_hist_destroy",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +33,8 @@ LIB_PATH = os.path.join(HERE, "libpr.so")
 PR_F64, PR_F32 = 64, 32
 PR_REUSE_COARSE, PR_SKIP_CONVERGED, PR_PROFILE, PR_AUTOTUNE = 1, 2, 4, 8
 PR_LAUNCH_BATCHED, PR_LAUNCH_GRAPH, PR_LAUNCH_PER_INSTANCE = 0, 1, 2
+PR_J_ADD, PR_J_MULT, PR_J_ROT, PR_J_QUANTILE = 0, 1, 2, 3
+PR_M_MARGINAL, PR_M_REWEIGHT, PR_M_RESAMPLE, PR_M_RESAMPLE_DET = 0, 1, 2, 3
 PHASES = ("fine", "restrict_fine", "coarse", "chain", "match", "restrict_new")
 
 _c_int, _c_i64, _c_u32, _c_u64, _c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
@@ -127,6 +133,20 @@ _SIGS = {
     "pr_parareal_batch_destroy": (_c_int, [_vp]),
     "pr_fine_adjoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64, _vp,
                                  _c_int, _vp, _vp, _c_int, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_hist_workspace_size": (ctypes.c_size_t, [_c_int, _c_int]),
+    "pr_hist_restrict": (_c_int, [_vp, _vp, _c_i64, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_hist_jump_workspace_size": (ctypes.c_size_t, [_c_int, _c_int]),
+    "pr_hist_jump": (_c_int, [_c_int, _vp, _vp, _vp, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_hist_match_workspace_size": (ctypes.c_size_t, [_c_i64, _c_int, _c_int]),
+    "pr_hist_match": (_c_int, [_c_int, _vp, _vp, _c_i64, _c_int, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, _vp, _c_i64,
+                               _vp, _vp, _vp, _c_u64, _c_u32, _c_int, _vp, ctypes.c_size_t, _vp]),
+    "pr_parareal_hist_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid),
+                                         _c_u64, _c_u32, _c_i64, _c_int, _c_int, _c_int, _vp, ctypes.POINTER(_vp)]),
+    "pr_parareal_hist_iterate": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "pr_parareal_hist_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp, _vp]),
+    "pr_parareal_hist_iteration": (_c_int, [_vp]),
+    "pr_parareal_hist_profile": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_int)]),
+    "pr_parareal_hist_destroy": (_c_int, [_vp]),
 }
 
 
@@ -338,3 +358,73 @@ def pr_parareal_batch_info(h):
 
 def pr_parareal_batch_destroy(h):
     _check(lib().pr_parareal_batch_destroy(h))
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def pr_hist_workspace_size(k, n_cells):
+    return lib().pr_hist_workspace_size(k, n_cells)
+
+
+def pr_hist_restrict(x, w, n, k, grid, rho, ws, stream=None):
+    g = grid.c()
+    _check(lib().pr_hist_restrict(_ptr(x), _ptr(w), n, k, ctypes.byref(g), _ptr(rho), _ptr(ws), _nbytes(ws),
+                                  _stream(stream)))
+
+
+def pr_hist_jump_workspace_size(k, n_cells):
+    return lib().pr_hist_jump_workspace_size(k, n_cells)
+
+
+def pr_hist_jump(kind, rho_c, rho_f, rho_cs, k, grid, rho_out, ws=None, stream=None):
+    g = grid.c()
+    _check(lib().pr_hist_jump(kind, _ptr(rho_c), _ptr(rho_f), _ptr(rho_cs), k, ctypes.byref(g), _ptr(rho_out),
+                              _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def pr_hist_match_workspace_size(n, k, n_cells):
+    return lib().pr_hist_match_workspace_size(n, k, n_cells)
+
+
+def pr_hist_match(kind, rho_t, rho_p, n, k, d, grid, x, y, w, prior_stride, x_out, y_out, w_out, ws, seed=0,
+                  instance=0, t_first=0, stream=None):
+    g = grid.c()
+    _check(lib().pr_hist_match(kind, _ptr(rho_t), _ptr(rho_p), n, k, d, ctypes.byref(g), _ptr(x), _ptr(y), _ptr(w),
+                               prior_stride, _ptr(x_out), _ptr(y_out), _ptr(w_out), seed, instance, t_first, _ptr(ws),
+                               _nbytes(ws), _stream(stream)))
+
+
+def pr_parareal_hist_create(sde, sched, grid, seed, instance, n, iterator, matching, flags=0, stream=None):
+    s, c, g = sde.c(), sched.c(), grid.c()
+    h = _vp()
+    _check(lib().pr_parareal_hist_create(ctypes.byref(s), ctypes.byref(c), ctypes.byref(g), seed, instance, n,
+                                         iterator, matching, flags, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_hist_iterate(h, n_iter, rho_ref=None, err_out=None, stream=None):
+    """err_out: host float64 numpy array of 2 * n_iter (error at N, max over n)."""
+    _check(lib().pr_parareal_hist_iterate(h, n_iter, _ptr(rho_ref),
+                                          err_out.ctypes.data_as(_vp) if err_out is not None else None,
+                                          _stream(stream)))
+
+
+def pr_parareal_hist_state(h, t, x=None, y=None, w=None, rho=None, stream=None):
+    _check(lib().pr_parareal_hist_state(h, t, _ptr(x), _ptr(y), _ptr(w), _ptr(rho), _stream(stream)))
+
+
+def pr_parareal_hist_iteration(h):
+    return lib().pr_parareal_hist_iteration(h)
+
+
+def pr_parareal_hist_profile(h):
+    ms = (_c_dbl * len(PHASES))()
+    it = _c_int(0)
+    _check(lib().pr_parareal_hist_profile(h, ms, ctypes.byref(it)))
+    return dict(zip(PHASES, list(ms))), it.value
+
+
+def pr_parareal_hist_destroy(h):
+    _check(lib().pr_parareal_hist_destroy(h))

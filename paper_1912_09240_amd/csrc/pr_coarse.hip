@@ -354,6 +354,16 @@ int coarse_jump(const Coarse *c, int n, const double *q_cur, const double *qf, c
     return PR_OK;
 }
 
+// rho_out[s] = max(E_{first+s} rho_in[s], 0) for s < count (cell masses).
+int coarse_apply(const Coarse *c, int first, int count, const double *rho_in, double *rho_out, hipStream_t st) {
+    if (count == 0) return PR_OK;
+    const GridDev &g = c->g;
+    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 3) / 4, count), dim3(256), sizeof(double) * g.cells, st,
+                       (const double *)c->E, (const int *)c->tau_id, first, rho_in, rho_out, g.cells);
+    PR_LAUNCHED();
+    return PR_OK;
+}
+
 int coarse_grid_nq(const Coarse *c) { return c->g.nq; }
 int coarse_grid_cells(const Coarse *c) { return c->g.cells; }
 

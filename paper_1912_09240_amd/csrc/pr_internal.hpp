@@ -226,6 +226,7 @@ int coarse_step(const Coarse *c, int first, int count, const double *q_in, int i
                 int out_stride, double *rho_out, hipStream_t st);
 int coarse_jump(const Coarse *c, int n, const double *q_cur, const double *qf, const double *qcs, double *q_next,
                 double *qc_out, hipStream_t st);
+int coarse_apply(const Coarse *c, int first, int count, const double *rho_in, double *rho_out, hipStream_t st);
 void coarse_free(Coarse *c);
 
 }  // namespace pr
