@@ -202,6 +202,53 @@ def batched_measure(torch, pr):
 HIGHDIM = dict(d=32, n=2 ** 20, dt=1e-4, T=5.0, K=32, eps=0.01, beta=2.0, lam=1.0, seed=0)
 
 
+HIST_COMBOS = [("quantile", "marginal"), ("quantile", "reweight"), ("quantile", "resample"),
+               ("quantile", "resample_det"), ("add", "resample"), ("mult", "resample"), ("rot", "resample")]
+
+
+def hist_measure(torch, pr, w, n, K, S, dt):
+    """Histogram-state iterations (Sec. 4 iterators, Sec. 5 matchings) on the
+    large workload: one warm-up and one timed iteration per combination with
+    the phase times, and the L2 error of the states' histograms to the
+    serial fine run after the timed iteration (device time from HIP events
+    recorded by the driver)."""
+    its = dict(add=pr.PR_J_ADD, mult=pr.PR_J_MULT, rot=pr.PR_J_ROT, quantile=pr.PR_J_QUANTILE)
+    mts = dict(marginal=pr.PR_M_MARGINAL, reweight=pr.PR_M_REWEIGHT, resample=pr.PR_M_RESAMPLE,
+               resample_det=pr.PR_M_RESAMPLE_DET)
+    sde = pr.Sde(lam=w["lam"], eps=w["eps"], beta=w["beta"])
+    sched = pr.Schedule(S, K, dt)
+    grid = pr.Grid(n_cells=w["cells"], n_q=w["nq"])
+    I = w["cells"]
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, w["seed"], 0, n, x, y)
+    ref = torch.empty((K + 1, I), dtype=torch.float64, device="cuda")
+    ws = torch.empty(pr.pr_hist_workspace_size(1, I), dtype=torch.uint8, device="cuda")
+    pr.pr_hist_restrict(x, None, n, 1, grid, ref[0], ws)
+    for s_ in range(K):
+        pr.pr_fine_propagate(sde, sched, w["seed"], 0, n, s_, 1, x, y)
+        pr.pr_hist_restrict(x, None, n, 1, grid, ref[s_ + 1], ws)
+    out = {}
+    for it, mt in HIST_COMBOS:
+        h = pr.pr_parareal_hist_create(sde, sched, grid, w["seed"], 0, n, its[it], mts[mt], flags=pr.PR_PROFILE)
+        try:
+            pr.pr_parareal_hist_iterate(h, 1)
+            p0, i0 = pr.pr_parareal_hist_profile(h)
+            err = np.zeros(2)
+            pr.pr_parareal_hist_iterate(h, 1, rho_ref=ref, err_out=err)
+            p1, i1 = pr.pr_parareal_hist_profile(h)
+        finally:
+            pr.pr_parareal_hist_destroy(h)
+        ph = {k: p1[k] - p0[k] for k in p1}
+        rest = ph["restrict_fine"] / 1e3
+        out[f"{it}+{mt}"] = dict(ms_per_iteration=sum(v for k, v in ph.items() if k != "restrict_new"),
+                                 phases_ms=ph, l2_error_at_T=float(err[0]), l2_error_max=float(err[1]),
+                                 restrict_fine_GBps=n * K * 8 / rest / 1e9)
+    return dict(workload="histogram states (1024 cells on [-3, 3]) of the large workload: P=2^20, 64 slices, "
+                         "1e5 steps of dt=1e-4; iterator + matching per entry; errors after two iterations",
+                combos=out)
+
+
 def highdim_measure(torch, pr):
     """Fast part in R^32 (dY_i = -(1/eps)(Y_i - a_i X) dt + ..., a_i from the
     seed): one fine sweep of all 32 slices (P = 2^20, 5e4 steps of 1e-4) in
@@ -336,6 +383,8 @@ def main():
     out["batched"] = batched_measure(torch, pr)
     log("fast part in R^32")
     out["high_dim"] = highdim_measure(torch, pr)
+    log("histogram states")
+    out["hist_states"] = hist_measure(torch, pr, w, n, K, S, dt)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

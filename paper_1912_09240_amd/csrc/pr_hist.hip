@@ -36,7 +36,7 @@ namespace pr {
 typedef unsigned __int128 u128;
 
 constexpr int HB_THREADS = 256;
-constexpr int HB_ITEMS = 16;
+constexpr int HB_ITEMS = 8;
 constexpr int HB_TILE = HB_THREADS * HB_ITEMS;  // particles per tile of the resampling
 constexpr int HB_MAX_CELLS = 1024;
 constexpr int FIX_W = 112;  // fraction bits of the histogram weights
@@ -99,9 +99,19 @@ __host__ __device__ inline uint64_t fix_weight(double w) {
     return (uint64_t)fix_floor(w, 64);
 }
 
-// U_j = floor(j T / P) + floor(k_j T / (P 2^32)).
-__host__ __device__ inline u128 slot_level(uint64_t j, uint32_t kj, u128 T, uint32_t P) {
-    return udiv128_32((u128)j * T, P) + udiv128_32(((u128)kj * T) >> 32, P);
+// U_j = floor(j T / P) + floor(k_j T / (P 2^32)), with T = qT P + rT:
+//   floor(j T / P)          = j qT + floor(j rT / P)
+//   floor(k T / (P 2^32))   = (k qT + floor(k rT / P)) >> 32
+// (j rT and k rT stay below 2^64, so two 64-bit divisions suffice).
+struct SlotConst {
+    u128 qT;
+    uint64_t rT;
+};
+
+__host__ __device__ inline u128 slot_level(uint64_t j, uint32_t kj, const SlotConst &c, uint32_t P) {
+    const u128 a = (u128)j * c.qT + (u128)((j * c.rT) / P);
+    const u128 b = ((u128)kj * c.qT + (u128)(((uint64_t)kj * c.rT) / P)) >> 32;
+    return a + b;
 }
 
 __device__ inline uint32_t slot_draw(Key key, uint32_t inst, uint32_t j, uint32_t t, int det) {
@@ -324,7 +334,78 @@ int hist_restrict(const double *x, const double *w, int64_t n, int64_t stride, i
 // Iterators, one slice per workgroup.
 // ---------------------------------------------------------------------------
 // Scratch of the quantile iterator per slice, in doubles.
-__host__ __device__ inline size_t jq_scratch_doubles(int cells) { return (size_t)17 * (cells + 1) + 8; }
+__host__ __device__ inline size_t jq_scratch_doubles(int cells) { return (size_t)6 * (cells + 1) + 8; }
+
+// Pool-adjacent-violators (equal weights) with the same additions, divisions
+// and comparisons as the textbook stack form: a new value starts a pool (sum
+// s, count c); while the pool below has a larger mean S/C it is merged
+// (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
+// SC = start << 16 | count, in position order); a pool of one value is read
+// back from v.  When the pool on top is a single value, nothing merges until
+// the next violation v[j] > v[j+1] of the input (vio, increasing): the
+// values in between stay single pools and are skipped.  One thread builds the
+// pools, the block then writes their means.
+__device__ inline void pava_sparse(const double *v, int L, const int *vio, int nv, double *S, int *SC,
+                                   int *npools) {
+#pragma clang fp contract(off)
+    int nb = 0, vi = 0;
+    int i = vio[0];
+    double tS = v[i], tM = tS;
+    int tC = 1, tSt = i;
+    ++i;
+    while (i < L) {
+        if (tC == 1) {
+            while (vi < nv && vio[vi] < i - 1) ++vi;
+            if (vi == nv) break;  // non-decreasing from v[i-1] on
+            const int jn = vio[vi];
+            if (jn > i - 1) {
+                tSt = jn;
+                tS = v[jn];
+                tM = tS;
+                i = jn + 1;
+            }
+        }
+        double s = v[i], m = s;
+        int c = 1, st = i;
+        bool below = true;
+        while (below && tM > m) {
+            s = s + tS;
+            c = c + tC;
+            st = tSt;
+            if (tSt == 0) {
+                below = false;
+            } else if (nb > 0 && (SC[nb - 1] >> 16) + (SC[nb - 1] & 0xFFFF) == tSt) {
+                --nb;
+                tS = S[nb];
+                tC = SC[nb] & 0xFFFF;
+                tSt = SC[nb] >> 16;
+                tM = tS / (double)tC;
+            } else {
+                tSt = tSt - 1;
+                tS = v[tSt];
+                tC = 1;
+                tM = tS / 1.0;
+            }
+            m = s / (double)c;
+        }
+        if (below && tC > 1) {
+            S[nb] = tS;
+            SC[nb] = (tSt << 16) | tC;
+            ++nb;
+        }
+        tS = s;
+        tC = c;
+        tSt = st;
+        tM = m;
+        ++i;
+    }
+    if (tC > 1) {
+        S[nb] = tS;
+        SC[nb] = (tSt << 16) | tC;
+        ++nb;
+    }
+    *npools = nb;
+}
 
 template <int KIND>
 __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict__ rc, const double *__restrict__ rf,
@@ -389,15 +470,16 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
             out[i] = t * t;
         }
     } else {
-        // quantile iterator on the union of the edge levels
-        double *sc = scratch + (size_t)s * jq_scratch_doubles(I);
+        // quantile iterator on the union of the edge levels.  LDS: the three
+        // edge cdfs (later the pool sums and the new edge cdf), the corrected
+        // quantiles, the pool counts; global scratch: merged and unique levels.
+        extern __shared__ double jq[];
         const int E = I + 1, T3 = 3 * E;
-        double *cc = sc, *cf = cc + E, *ccs = cf + E;  // cdfs at the edges
-        double *merged = ccs + E;                       // [3E]
-        double *lev = merged + T3;                      // [<= 3E] unique levels
-        double *qt = lev + T3;                          // [<= 3E]
-        double *pS = qt + T3;                           // [3E] PAVA sums
-        int *pC = (int *)(pS + T3);                     // [3E] PAVA counts (fits in 1.5E doubles)
+        double *cc = jq, *cf = cc + E, *ccs = cf + E;  // [3E]
+        double *qt = jq + T3;                           // [<= 3E]
+        int *pC = (int *)(jq + 2 * T3);                 // [<= 3E]
+        double *sc = scratch + (size_t)s * jq_scratch_doubles(I);
+        double *merged = sc, *lev = sc + T3;            // [3E] each
         __shared__ int nU, bad;
         const int wave = threadIdx.x >> 6;
         if (wave == 0) wave_running_sum([&](int i) { return rc[i]; }, I, cc);
@@ -416,21 +498,28 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
             merged[pos] = v;
         }
         __syncthreads();
-        // unique levels: compaction of the first of every run of equal values
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            int base = 0;
-            for (int c0 = 0; c0 < T3; c0 += 64) {
-                const int i = c0 + lane;
-                const bool keep = i < T3 && (i == 0 || merged[i] != merged[i - 1]);
-                const uint64_t bal = __ballot(keep);
-                const int off = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                if (keep) lev[base + off] = merged[i];
-                base += __popcll(bal);
+        // unique levels: compaction of the first of every run of equal values,
+        // every thread owning a contiguous chunk of the merged levels
+        {
+            const int per = (T3 + HB_THREADS - 1) / HB_THREADS;
+            const int i0 = threadIdx.x * per, i1 = min(i0 + per, T3);
+            int cnt = 0;
+            for (int i = i0; i < i1; ++i) cnt += (i == 0 || merged[i] != merged[i - 1]) ? 1 : 0;
+            __shared__ int wsum[HB_THREADS / 64];
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            int inc = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(inc, off);
+                if (lane >= off) inc += t;
             }
-            if (lane == 0) nU = base;
+            if (lane == 63) wsum[w] = inc;
+            __syncthreads();
+            int base = inc - cnt;
+            for (int k2 = 0; k2 < w; ++k2) base += wsum[k2];
+            for (int i = i0; i < i1; ++i)
+                if (i == 0 || merged[i] != merged[i - 1]) lev[base++] = merged[i];
+            if (threadIdx.x == HB_THREADS - 1) nU = base;
         }
-        if (threadIdx.x == 0) bad = 0;
         __syncthreads();
         const int U = nU;
         for (int j = threadIdx.x; j < U; j += blockDim.x) {
@@ -438,13 +527,43 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
             qt[j] = quantile_hist(rf, cf, g, p) + (quantile_hist(rc, cc, g, p) - quantile_hist(rcs, ccs, g, p));
         }
         __syncthreads();
-        for (int j = threadIdx.x; j + 1 < U; j += blockDim.x)
-            if (qt[j] > qt[j + 1]) bad = 1;
+        // violations qt[j] > qt[j+1], in increasing j, compacted into vio (the
+        // upper half of the cdfs' LDS; the pools' sums use the lower half)
+        int *vio = (int *)(jq + (T3 + 1) / 2);
+        {
+            const int per = (U + HB_THREADS - 1) / HB_THREADS;
+            const int j0 = threadIdx.x * per, j1 = min(j0 + per, U - 1);
+            int cnt = 0;
+            for (int j = j0; j < j1; ++j) cnt += qt[j] > qt[j + 1] ? 1 : 0;
+            __shared__ int vsum[HB_THREADS / 64];
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            int inc = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(inc, off);
+                if (lane >= off) inc += t;
+            }
+            if (lane == 63) vsum[w] = inc;
+            __syncthreads();
+            int base = inc - cnt;
+            for (int k2 = 0; k2 < w; ++k2) base += vsum[k2];
+            for (int j = j0; j < j1; ++j)
+                if (qt[j] > qt[j + 1]) vio[base++] = j;
+            if (threadIdx.x == HB_THREADS - 1) bad = base;
+        }
         __syncthreads();
-        if (bad && threadIdx.x == 0) pava_serial(qt, U, pS, pC);
+        if (bad > 0) {  // the cdfs are no longer needed: their LDS holds the pools
+            __shared__ int npools;
+            if (threadIdx.x == 0) pava_sparse(qt, U, vio, bad, jq, pC, &npools);
+            __syncthreads();
+            for (int b = threadIdx.x; b < npools; b += blockDim.x) {
+                const int c = pC[b] & 0xFFFF, st = pC[b] >> 16;
+                const double mean = jq[b] / (double)c;
+                for (int t = 0; t < c; ++t) qt[st + t] = mean;
+            }
+        }
         __syncthreads();
         // cdf at the edges: inf{p : q(p) >= x_i} on the piecewise-linear q
-        double *ct = merged;  // reuse [E]
+        double *ct = jq;  // [E], over the pool sums
         for (int i = threadIdx.x; i < E; i += blockDim.x) {
             double v;
             if (i == 0) {
@@ -468,6 +587,8 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
     }
 }
 
+static size_t jq_lds_bytes(int cells) { return (sizeof(double) * 2 + sizeof(int)) * 3 * (size_t)(cells + 1); }
+
 size_t hist_jump_ws_bytes(int k, int cells) { return sizeof(double) * jq_scratch_doubles(cells) * (size_t)k + 256; }
 
 int hist_jump_launch(int kind, const double *rc, const double *rf, const double *rcs, int64_t in_stride, int k,
@@ -487,8 +608,8 @@ int hist_jump_launch(int kind, const double *rc, const double *rf, const double 
                                out_stride, g, scratch);
             break;
         default:
-            hipLaunchKernelGGL(hist_jump<PR_J_QUANTILE>, dim3(k), dim3(HB_THREADS), 0, st, rc, rf, rcs, in_stride, out,
-                               out_stride, g, scratch);
+            hipLaunchKernelGGL(hist_jump<PR_J_QUANTILE>, dim3(k), dim3(HB_THREADS), jq_lds_bytes(g.cells), st, rc, rf,
+                               rcs, in_stride, out, out_stride, g, scratch);
     }
     PR_LAUNCHED();
     return PR_OK;
@@ -512,30 +633,43 @@ __global__ void __launch_bounds__(HB_THREADS) match_tables(const double *__restr
     const int wave = threadIdx.x >> 6;
     if (wave == 0) wave_running_sum([&](int i) { return rp[i]; }, I, cp);
     if (wave == 1) wave_running_sum([&](int i) { return rt[i]; }, I, ctg);
-    if (want_ratio && threadIdx.x == 128) {
+    if (want_ratio) {
         // the target mass of cells without prior particles goes to the
         // nearest supported cells, half to each side, in increasing cell order
-        for (int i = 0; i < I; ++i) ratio[i] = rp[i] > 0.0 ? rt[i] : 0.0;
-        int left = -1;
-        for (int i = 0; i < I; ++i) {
-            if (rp[i] > 0.0) {
-                left = i;
-                continue;
-            }
-            if (rt[i] == 0.0) continue;
-            int right = i + 1;
-            while (right < I && !(rp[right] > 0.0)) ++right;
-            if (left >= 0 && right < I) {
-                const double half = 0.5 * rt[i];
-                ratio[left] = ratio[left] + half;
-                ratio[right] = ratio[right] + half;
-            } else if (left >= 0) {
-                ratio[left] = ratio[left] + rt[i];
-            } else if (right < I) {
-                ratio[right] = ratio[right] + rt[i];
+        __shared__ double r[HB_MAX_CELLS], tg[HB_MAX_CELLS];
+        __shared__ int sup[HB_MAX_CELLS], nxt[HB_MAX_CELLS + 1];
+        for (int i = threadIdx.x; i < I; i += blockDim.x) {
+            sup[i] = rp[i] > 0.0 ? 1 : 0;
+            tg[i] = rt[i];
+            r[i] = sup[i] ? tg[i] : 0.0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 128) {
+            // nxt[i]: first supported cell at or after i (I if none)
+            nxt[I] = I;
+            for (int i = I - 1; i >= 0; --i) nxt[i] = sup[i] ? i : nxt[i + 1];
+            int left = -1;
+            for (int i = 0; i < I; ++i) {
+                if (sup[i]) {
+                    left = i;
+                    continue;
+                }
+                const double m = tg[i];
+                if (m == 0.0) continue;
+                const int right = nxt[i + 1];
+                if (left >= 0 && right < I) {
+                    const double half = 0.5 * m;
+                    r[left] = r[left] + half;
+                    r[right] = r[right] + half;
+                } else if (left >= 0) {
+                    r[left] = r[left] + m;
+                } else if (right < I) {
+                    r[right] = r[right] + m;
+                }
             }
         }
-        for (int i = 0; i < I; ++i) ratio[i] = rp[i] > 0.0 ? ratio[i] / rp[i] : 0.0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < I; i += blockDim.x) ratio[i] = sup[i] ? r[i] / rp[i] : 0.0;
     }
 }
 
@@ -591,35 +725,68 @@ __global__ void __launch_bounds__(HB_THREADS) reweight_kernel(HMatchArgs a, HGri
         wo[p] = (w ? w[p] : w0) * ratio[hcell(g, x[p])];
 }
 
+// Inclusive prefix of one u128 per thread over the block, in thread order;
+// *total receives the block's sum.
+__device__ inline u128 block_inclusive_u128(u128 v, u128 *total) {
+    __shared__ uint64_t wt[HB_THREADS / 64][2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u128 inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long lo = __shfl_up((unsigned long long)(uint64_t)inc, off);
+        const unsigned long long hi = __shfl_up((unsigned long long)(uint64_t)(inc >> 64), off);
+        if (lane >= off) inc += ((u128)hi << 64) | (u128)lo;
+    }
+    if (lane == 63) {
+        wt[w][0] = (uint64_t)inc;
+        wt[w][1] = (uint64_t)(inc >> 64);
+    }
+    __syncthreads();
+    u128 pre = 0, tot = 0;
+    for (int k2 = 0; k2 < HB_THREADS / 64; ++k2) {
+        const u128 t = (u128)wt[k2][0] | ((u128)wt[k2][1] << 64);
+        if (k2 < w) pre += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc;
+}
+
+// The reweighting ratios of slice s into LDS.
+__device__ inline void load_ratio(const HMatchArgs &a, const HGrid &g, int s, double *r) {
+    const int I = g.cells;
+    const double *ratio = a.tab + (size_t)s * 3 * (I + 1) + 2 * (I + 1);
+    for (int i = threadIdx.x; i < I; i += blockDim.x) r[i] = ratio[i];
+    __syncthreads();
+}
+
 // Resampling, pass 1: exact tile sums of the fixed-point weights.  Grid
-// (tiles, k); one tile is HB_TILE particles.
+// (tiles, k); a tile is HB_TILE particles, row i of a tile the particles
+// tile * HB_TILE + i * HB_THREADS + thread.
 __global__ void __launch_bounds__(HB_THREADS) resample_tile_sums(HMatchArgs a, HGrid g, double w0, int ntile,
                                                                  uint64_t *__restrict__ tsum) {
-    const int s = blockIdx.y, I = g.cells;
-    const double *ratio = a.tab + (size_t)s * 3 * (I + 1) + 2 * (I + 1);
+    __shared__ double r[HB_MAX_CELLS];
+    const int s = blockIdx.y;
+    load_ratio(a, g, s, r);
     const double *x = a.x + (int64_t)s * a.x_stride;
     const double *w = a.w ? a.w + (int64_t)s * a.x_stride : nullptr;
-    const int64_t p0 = (int64_t)blockIdx.x * HB_TILE + (int64_t)threadIdx.x * HB_ITEMS;
+    const int64_t p0 = (int64_t)blockIdx.x * HB_TILE + threadIdx.x;
     u128 acc = 0;
     for (int i = 0; i < HB_ITEMS; ++i) {
-        const int64_t p = p0 + i;
-        if (p < a.n) acc += (u128)fix_weight((w ? w[p] : w0) * ratio[hcell(g, x[p])]);
+        const int64_t p = p0 + (int64_t)i * HB_THREADS;
+        if (p < a.n) acc += (u128)fix_weight((w ? w[p] : w0) * r[hcell(g, x[p])]);
     }
-    __shared__ uint64_t part[HB_THREADS][2];
-    part[threadIdx.x][0] = (uint64_t)acc;
-    part[threadIdx.x][1] = (uint64_t)(acc >> 64);
-    __syncthreads();
+    u128 tot;
+    (void)block_inclusive_u128(acc, &tot);
     if (threadIdx.x == 0) {
-        u128 t = 0;
-        for (int i = 0; i < HB_THREADS; ++i) t += (u128)part[i][0] | ((u128)part[i][1] << 64);
         uint64_t *o = tsum + 2 * ((int64_t)s * ntile + blockIdx.x);
-        o[0] = (uint64_t)t;
-        o[1] = (uint64_t)(t >> 64);
+        o[0] = (uint64_t)tot;
+        o[1] = (uint64_t)(tot >> 64);
     }
 }
 
 // Pass 2: exclusive prefix over the tiles of every slice, and the total.
-__global__ void resample_tile_scan(uint64_t *__restrict__ tsum, int ntile, uint64_t *__restrict__ total) {
+__global__ void resample_tile_scan(uint64_t *__restrict__ tsum, int ntile, int64_t P, uint64_t *__restrict__ total) {
     const int s = blockIdx.x;
     if (threadIdx.x != 0) return;
     uint64_t *t = tsum + 2 * (int64_t)s * ntile;
@@ -630,18 +797,39 @@ __global__ void resample_tile_scan(uint64_t *__restrict__ tsum, int ntile, uint6
         t[2 * i + 1] = (uint64_t)(run >> 64);
         run += v;
     }
-    total[2 * s] = (uint64_t)run;
-    total[2 * s + 1] = (uint64_t)(run >> 64);
+    total[5 * s] = (uint64_t)run;
+    total[5 * s + 1] = (uint64_t)(run >> 64);
+    const u128 qT = udiv128_32(run, (uint32_t)P);
+    total[5 * s + 2] = (uint64_t)qT;
+    total[5 * s + 3] = (uint64_t)(qT >> 64);
+    total[5 * s + 4] = (uint64_t)(run - qT * (u128)P);
 }
 
-// Pass 3: every particle p writes the slots j with C_p <= U_j < C_{p+1}
-// (the last particle takes every slot from C_{P-1} on).
+// first slot j in [0, P] with U_j >= C (U is non-decreasing in j), from the
+// estimate j = C P / T
+__device__ inline int64_t first_slot_at(u128 C, u128 T, double Td, const SlotConst &sc, uint32_t P, Key key,
+                                        uint32_t inst, uint32_t tpnt, int det) {
+    if (C >= T) return (int64_t)P;
+    int64_t j = (int64_t)(fix_to_double(C, 0) / Td * (double)P);
+    j = j < 0 ? 0 : (j > (int64_t)P ? (int64_t)P : j);
+    while (j > 0 && slot_level((uint64_t)(j - 1), slot_draw(key, inst, (uint32_t)(j - 1), tpnt, det), sc, P) >= C) --j;
+    while (j < (int64_t)P && slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), sc, P) < C) ++j;
+    return j;
+}
+
+// Pass 3: the slots of a tile.  The block lays the cumulative weights of its
+// particles out in LDS, finds the slots j whose level U_j falls inside the
+// tile's weight range, and gives each of them the particle p with
+// C_p <= U_j < C_{p+1} (the first whose inclusive sum exceeds U_j).
 __global__ void __launch_bounds__(HB_THREADS) resample_slots_kernel(HMatchArgs a, HGrid g, double w0, int ntile,
                                                                     const uint64_t *__restrict__ tsum,
                                                                     const uint64_t *__restrict__ total, Key key,
                                                                     uint32_t inst, int t_first, int det) {
-    const int s = blockIdx.y, I = g.cells;
-    const double *ratio = a.tab + (size_t)s * 3 * (I + 1) + 2 * (I + 1);
+    __shared__ double r[HB_MAX_CELLS];
+    __shared__ uint64_t cum[HB_TILE][2];  // inclusive cumulative weight of every particle of the tile
+    __shared__ int64_t jr[2];
+    const int s = blockIdx.y;
+    load_ratio(a, g, s, r);
     const double *x = a.x + (int64_t)s * a.x_stride;
     const double *w = a.w ? a.w + (int64_t)s * a.x_stride : nullptr;
     const double *y = a.y + (int64_t)s * a.x_stride * a.d;
@@ -649,61 +837,50 @@ __global__ void __launch_bounds__(HB_THREADS) resample_slots_kernel(HMatchArgs a
     double *yo = a.yo + (int64_t)s * a.o_stride * a.d;
     double *wo = a.wo + (int64_t)s * a.o_stride;
     const uint32_t P = (uint32_t)a.n;
-    const u128 T = (u128)total[2 * s] | ((u128)total[2 * s + 1] << 64);
+    const u128 T = (u128)total[5 * s] | ((u128)total[5 * s + 1] << 64);
+    SlotConst sc;
+    sc.qT = (u128)total[5 * s + 2] | ((u128)total[5 * s + 3] << 64);
+    sc.rT = total[5 * s + 4];
+    const double Td = fix_to_double(T, 0);
     const uint64_t *tp = tsum + 2 * ((int64_t)s * ntile + blockIdx.x);
-    const u128 tile_pre = (u128)tp[0] | ((u128)tp[1] << 64);
-    const int64_t p0 = (int64_t)blockIdx.x * HB_TILE + (int64_t)threadIdx.x * HB_ITEMS;
-    uint64_t q[HB_ITEMS];
-    u128 mine = 0;
-    for (int i = 0; i < HB_ITEMS; ++i) {
-        const int64_t p = p0 + i;
-        q[i] = p < a.n ? fix_weight((w ? w[p] : w0) * ratio[hcell(g, x[p])]) : 0ull;
-        mine += (u128)q[i];
-    }
-    // exclusive prefix of the per-thread sums over the block
-    __shared__ uint64_t part[HB_THREADS][2];
-    part[threadIdx.x][0] = (uint64_t)mine;
-    part[threadIdx.x][1] = (uint64_t)(mine >> 64);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        u128 run = 0;
-        for (int i = 0; i < HB_THREADS; ++i) {
-            const u128 v = (u128)part[i][0] | ((u128)part[i][1] << 64);
-            part[i][0] = (uint64_t)run;
-            part[i][1] = (uint64_t)(run >> 64);
-            run += v;
-        }
-    }
-    __syncthreads();
-    u128 C = tile_pre + ((u128)part[threadIdx.x][0] | ((u128)part[threadIdx.x][1] << 64));
+    const u128 start = (u128)tp[0] | ((u128)tp[1] << 64);
     const uint32_t tpnt = (uint32_t)(t_first + s);
+    const int64_t t0 = (int64_t)blockIdx.x * HB_TILE;
+    const int np = (int)((a.n - t0) < HB_TILE ? (a.n - t0) : HB_TILE);
+    u128 row0 = start;
     for (int i = 0; i < HB_ITEMS; ++i) {
-        const int64_t p = p0 + i;
-        if (p >= a.n) break;
-        const u128 C1 = C + (u128)q[i];
-        const bool last = p == (int64_t)P - 1;
-        if (q[i] != 0 || last) {
-            // first slot j with U_j >= C: start from the level estimate
-            int64_t j = (int64_t)(fix_to_double(C, 0) / fix_to_double(T, 0) * (double)P);
-            j = j < 0 ? 0 : (j > (int64_t)P ? (int64_t)P : j);
-            while (j > 0 && slot_level((uint64_t)(j - 1), slot_draw(key, inst, (uint32_t)(j - 1), tpnt, det), T, P) >= C)
-                --j;
-            while (j < (int64_t)P && slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), T, P) < C)
-                ++j;
-            for (; j < (int64_t)P; ++j) {
-                if (!last && slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), T, P) >= C1) break;
-                xo[j] = x[p];
-                for (int c = 0; c < a.d; ++c) yo[(int64_t)c * a.n + j] = y[(int64_t)c * a.n + p];
-                wo[j] = w0;
-            }
+        const int idx = i * HB_THREADS + threadIdx.x;
+        const int64_t p = t0 + idx;
+        const uint64_t q = idx < np ? fix_weight((w ? w[p] : w0) * r[hcell(g, x[p])]) : 0ull;
+        u128 rowtot;
+        const u128 c = row0 + block_inclusive_u128((u128)q, &rowtot);
+        cum[idx][0] = (uint64_t)c;
+        cum[idx][1] = (uint64_t)(c >> 64);
+        row0 += rowtot;
+    }
+    if (threadIdx.x == 0) jr[0] = first_slot_at(start, T, Td, sc, P, key, inst, tpnt, det);
+    if (threadIdx.x == 64)
+        jr[1] = (int)blockIdx.x == ntile - 1 ? (int64_t)P : first_slot_at(row0, T, Td, sc, P, key, inst, tpnt, det);
+    __syncthreads();
+    for (int64_t j = jr[0] + threadIdx.x; j < jr[1]; j += HB_THREADS) {
+        const u128 U = slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), sc, P);
+        int lo = 0, hi = np - 1;  // first idx with cum[idx] > U (the last particle takes the rest)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const u128 cm = (u128)cum[mid][0] | ((u128)cum[mid][1] << 64);
+            if (cm > U) hi = mid;
+            else lo = mid + 1;
         }
-        C = C1;
+        const int64_t p = t0 + lo;
+        xo[j] = x[p];
+        for (int c = 0; c < a.d; ++c) yo[(int64_t)c * a.n + j] = y[(int64_t)c * a.n + p];
+        wo[j] = w0;
     }
 }
 
 size_t hist_match_ws_bytes(int64_t n, int k, int cells) {
     const int64_t ntile = (n + HB_TILE - 1) / HB_TILE;
-    return sizeof(double) * match_tab_doubles(k, cells) + sizeof(uint64_t) * 2 * ((size_t)ntile * k + k) + 512;
+    return sizeof(double) * match_tab_doubles(k, cells) + sizeof(uint64_t) * (2 * (size_t)ntile * k + 5 * (size_t)k) + 512;
 }
 
 int hist_match(int kind, const HMatchArgs &a0, int k, const HGrid &g, Key key, uint32_t inst, int t_first, void *ws,
@@ -734,7 +911,7 @@ int hist_match(int kind, const HMatchArgs &a0, int k, const HGrid &g, Key key, u
     const dim3 tgrid((unsigned)ntile, (unsigned)k);
     hipLaunchKernelGGL(resample_tile_sums, tgrid, dim3(HB_THREADS), 0, st, a, g, w0, ntile, tsum);
     PR_LAUNCHED();
-    hipLaunchKernelGGL(resample_tile_scan, dim3(k), dim3(64), 0, st, tsum, ntile, total);
+    hipLaunchKernelGGL(resample_tile_scan, dim3(k), dim3(64), 0, st, tsum, ntile, a.n, total);
     PR_LAUNCHED();
     hipLaunchKernelGGL(resample_slots_kernel, tgrid, dim3(HB_THREADS), 0, st, a, g, w0, ntile, (const uint64_t *)tsum,
                        (const uint64_t *)total, key, inst, t_first, kind == PR_M_RESAMPLE_DET ? 1 : 0);
