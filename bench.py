@@ -49,8 +49,8 @@ VALU_PEAK = 256 * 64 * 2.4e9
 # HBM bytes of one launch of the fine kernel (all 64 slices) from two
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
 # + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
-FINE_TRAFFIC_BYTES = (524365 * 2 + 1048576) * 1024
-FINE_SOURCES_SHA256 = "02ec1f73c754ad165a5680dc8419e21ca120ad1fafc14e275f94f381ecab0afb"
+FINE_TRAFFIC_BYTES = (524366 * 2 + 1048576) * 1024
+FINE_SOURCES_SHA256 = "1df447b57830fa1fad191592ba5875a22f2ecc753e078a0daf1e173a0e96df8f"
 FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
                 "pr_noise_tables.inc"]
 
