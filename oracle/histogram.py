@@ -47,6 +47,7 @@ import math
 
 import numpy as np
 
+from . import chem as _chem
 from . import coarse as _coarse
 from . import iterate as _iterate
 from . import particles as _particles
@@ -297,25 +298,40 @@ class HistEnsemble:
         return self._rho
 
 
+def _model(model):
+    """(initial ensemble, Euler-Maruyama, coarse propagator class) of the
+    double-well model (an oracle.particles.Sde) or of the chemical-reaction
+    model (an oracle.chem.Chem)."""
+    if isinstance(model, _chem.Chem):
+        return ((lambda s, i, n: _chem.init_ensemble(model, s, i, n)),
+                (lambda s, i, x, y, a, b, dt: _chem.em_propagate(model, s, i, x, y, a, b, dt)),
+                (lambda g: _chem.Propagator(g, model)))
+    return ((lambda s, i, n: _particles.init_ensemble(model, s, i, n)),
+            (lambda s, i, x, y, a, b, dt: _particles.em_propagate(model, s, i, x, y, a, b, dt)),
+            (lambda g: _coarse.Propagator(g, model)))
+
+
 def micmac_parareal_hist(sde, seed, inst, n_particles, T, dt, n_slices, grid, iterator, matching):
     """The histogram-state micro-macro parareal iteration at k = 0 (the
-    generic driver of iterate.Parareal with these operators).  The
+    generic driver of iterate.Parareal with these operators), for either
+    model (`sde` an oracle.particles.Sde or an oracle.chem.Chem).  The
     resampling draws its stratified numbers per time point n of the state it
     produces."""
+    init, propagate, propagator = _model(sde)
     S, dt_eff = _iterate.total_steps(T, dt)
     bounds = _iterate.slice_bounds(S, n_slices)
-    prop = _coarse.Propagator(grid, sde)
+    prop = propagator(grid)
     taus = {}
     for n in range(n_slices):
         L = bounds[n + 1] - bounds[n]
         if L not in taus:
             taus[L] = prop.expm(L * dt_eff)
     E = [taus[bounds[n + 1] - bounds[n]] for n in range(n_slices)]
-    x0, y0 = _particles.init_ensemble(sde, seed, inst, n_particles)
+    x0, y0 = init(seed, inst, n_particles)
     w0 = equal_weights(n_particles)
 
     def fine(n, u):
-        x, y = _particles.em_propagate(sde, seed, inst, u.x, u.y, bounds[n], bounds[n + 1], dt_eff)
+        x, y = propagate(seed, inst, u.x, u.y, bounds[n], bounds[n + 1], dt_eff)
         return HistEnsemble(x, y, u.w)
 
     def coarse(n, rho):
@@ -350,3 +366,19 @@ def hist_error(rho, rho_ref):
     """L2 error of two histograms (the error measure of Sec. 6)."""
     d = np.asarray(rho) - np.asarray(rho_ref)
     return math.sqrt(float(np.sum(d * d)))
+
+
+def serial_hist(model, seed, inst, n_particles, T, dt, n_slices, grid):
+    """Histograms at the slice ends t_n of a serial fine run of n_particles
+    (the reference of the paper's error plots uses ten times the parareal
+    ensemble size, Sec. 6)."""
+    init, propagate, _ = _model(model)
+    S, dt_eff = _iterate.total_steps(T, dt)
+    bounds = _iterate.slice_bounds(S, n_slices)
+    x, y = init(seed, inst, n_particles)
+    w = equal_weights(n_particles)
+    out = [hist_restrict(x, w, grid)]
+    for n in range(n_slices):
+        x, y = propagate(seed, inst, x, y, bounds[n], bounds[n + 1], dt_eff)
+        out.append(hist_restrict(x, w, grid))
+    return np.array(out)

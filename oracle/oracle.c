@@ -295,3 +295,83 @@ void or_em_tangent(const or_sde *s, uint64_t seed, uint32_t inst, int64_t n,
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Chemical-reaction system (Sec. 2.1.2): slow X, fast Y, multiplicative      */
+/* noise.  The SDE is eq. (SDEx)/(SDEy) with the diffusions                   */
+/*   D(x, y) = (k4 y + k5 x)/2,                                               */
+/*   E(y)    = (k0 + k1 y + k2 y(y-1) + k3 y(y-1)(y-2))/2,                    */
+/* which are half the summed propensities of the reactions                    */
+/*   0 -> Y (k0), Y -> 0 (k1 y), 2Y -> 3Y (k2 y(y-1)), 3Y -> 2Y               */
+/*   (k3 y(y-1)(y-2)), Y -> Y + X (k4 y), X -> 0 (k5 x).                      */
+/* Reading of the potentials: the drifts are the chemical-Langevin drifts of  */
+/* those reactions,                                                           */
+/*   -dF/dx = k4 y - k5 x,                                                    */
+/*   -dG/dy = k0 - k1 y + k2 y(y-1) - k3 y(y-1)(y-2),                         */
+/* i.e. F = -k4 x y + k5 x^2/2 and                                            */
+/* G = -k0 y + k1 y^2/2 - k2 y^2 (y/3 - 1/2) + k3 y^2 (y/2 - 1)^2.  The signs  */
+/* printed for the k1, k2, k3 and k5 terms give drifts without a stable state  */
+/* (X and Y grow without bound), which contradicts the bounded grid and the   */
+/* bistability of the fast variable that the experiments rely on.            */
+/* Reading of D >= 0: the diffusions enter the square root as max(., 0).      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double tau_x;     /* slow time scale */
+    double eps;       /* time-scale separation */
+    double k[6];      /* reaction rates k0..k5 */
+    double x0_mean, x0_sd, y0_mean, y0_sd;  /* lognormal initial law */
+} or_chem;
+
+/* Initial law (Sec. 6): independent lognormal X0, Y0 with the given mean and
+ * standard deviation: log X0 ~ N(mu, s^2), s^2 = log(1 + (sd/mean)^2),
+ * mu = log(mean) - s^2/2.  X0 from normal 0, Y0 from normal 1 of the pair
+ * (tag 1, m = 0, p, j = 0). */
+void or_chem_init(const or_chem *c, uint64_t seed, uint32_t inst, int64_t n, double *x, double *y)
+{
+    double vx = log(1.0 + (c->x0_sd / c->x0_mean) * (c->x0_sd / c->x0_mean));
+    double vy = log(1.0 + (c->y0_sd / c->y0_mean) * (c->y0_sd / c->y0_mean));
+    double mx = log(c->x0_mean) - 0.5 * vx, my = log(c->y0_mean) - 0.5 * vy;
+    double sx = sqrt(vx), sy = sqrt(vy);
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        double z0, z1;
+        or_normal_pair(seed, inst, 1u, 0u, (uint32_t)p, 0u, &z0, &z1);
+        x[p] = exp(mx + sx * z0);
+        y[p] = exp(my + sy * z1);
+    }
+}
+
+/* Euler-Maruyama (Sec. 2.1.3 eq. (EMx)/(EMy)) for the system above, drift and
+ * diffusion at the old state, normals (z0, z1) of pair (tag 0, m, p, j = 0):
+ *   X' = X + (dt/tau_x)(k4 Y - k5 X) + sqrt(2 max(D, 0) dt/tau_x) z0
+ *   Y' = Y + (dt/eps) b(Y)          + sqrt(2 max(E, 0) dt/eps) z1
+ * for global steps [m_begin, m_end) of particles p0 .. p0+n-1. */
+void or_chem_em(const or_chem *c, uint64_t seed, uint32_t inst, int64_t p0, int64_t n, int64_t m_begin,
+                int64_t m_end, double dt, double *x, double *y)
+{
+    const double *k = c->k;
+    double ax = dt / c->tau_x, ay = dt / c->eps;
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        uint32_t p = (uint32_t)(p0 + q);
+        double xv = x[q], yv = y[q];
+        for (int64_t m = m_begin; m < m_end; ++m) {
+            double z0, z1;
+            or_normal_pair(seed, inst, 0u, (uint32_t)m, p, 0u, &z0, &z1);
+            double y1 = yv * (yv - 1.0);
+            double y2 = y1 * (yv - 2.0);
+            double bx = k[4] * yv - k[5] * xv;
+            double by = k[0] - k[1] * yv + k[2] * y1 - k[3] * y2;
+            double D = 0.5 * (k[4] * yv + k[5] * xv);
+            double E = 0.5 * (k[0] + k[1] * yv + k[2] * y1 + k[3] * y2);
+            if (D < 0.0) D = 0.0;
+            if (E < 0.0) E = 0.0;
+            double xn = xv + ax * bx + sqrt(2.0 * D * ax) * z0;
+            double yn = yv + ay * by + sqrt(2.0 * E * ay) * z1;
+            xv = xn;
+            yv = yn;
+        }
+        x[q] = xv;
+        y[q] = yv;
+    }
+}
