@@ -379,6 +379,70 @@ int pr_parareal_hist_iteration(const void *h);
 int pr_parareal_hist_profile(const void *h, double *ms_out, int *iterations);
 int pr_parareal_hist_destroy(void *h);
 
+/*
+ * Chemical-reaction system (Sec. 2.1.2, the paper's own workload): slow X,
+ * fast Y (d = 1), multiplicative noise, eq. (SDEx)/(SDEy) with
+ *   D(x, y) = (k4 y + k5 x)/2,
+ *   E(y)    = (k0 + k1 y + k2 y(y-1) + k3 y(y-1)(y-2))/2,
+ * half the summed propensities of the reactions 0 -> Y (k0), Y -> 0 (k1 y),
+ * 2Y -> 3Y (k2 y(y-1)), 3Y -> 2Y (k3 y(y-1)(y-2)), Y -> Y + X (k4 y),
+ * X -> 0 (k5 x), and the drifts of those reactions (chemical Langevin form):
+ *   -dF/dx = k4 y - k5 x,  -dG/dy = k0 - k1 y + k2 y(y-1) - k3 y(y-1)(y-2).
+ * D and E enter the square roots as max(., 0).  Table 1 of the paper gives
+ * tau_x = 25, eps = 2.5e-2, k = (60, 1, 4.8e-3, k3, 0.833, 1); with k3 read
+ * as 0.666e-5 the fast variable is bistable (stable states near 105 and 408).
+ * Initial law (Sec. 6): independent lognormal X0, Y0 with the given means
+ * and standard deviations.
+ */
+typedef struct pr_chem {
+    double tau_x;              /* slow time scale, > 0                          */
+    double eps;                /* time-scale separation, > 0                    */
+    double k[6];               /* reaction rates k0..k5, >= 0, k4, k5 > 0       */
+    double x0_mean, x0_sd;     /* lognormal X0: mean > 0, sd >= 0               */
+    double y0_mean, y0_sd;     /* lognormal Y0: mean > 0, sd >= 0               */
+} pr_chem;
+
+/* Initial ensemble: log X0 = mu_x + s_x z0, log Y0 = mu_y + s_y z1 with
+ * s^2 = log(1 + sd^2/mean^2), mu = log(mean) - s^2/2, (z0, z1) the normal
+ * pair (tag 1, m = 0, p, j = 0).  x, y: device, [n] FP64. */
+int pr_chem_init_ensemble(const pr_chem *c, uint64_t seed, uint32_t instance, int64_t n, double *x, double *y,
+                          void *stream);
+
+/* Fine propagator of the chemical system: Euler-Maruyama (eq. (EMx)/(EMy)),
+ * drift and diffusion at the old state, normals (z0, z1) of pair
+ * (tag 0, m, p, j = 0):
+ *   X' = X + (dt/tau_x)(k4 Y - k5 X) + sqrt(2 max(D, 0) dt/tau_x) z0
+ *   Y' = Y + (dt/eps) b(Y)          + sqrt(2 max(E, 0) dt/eps) z1
+ * over every slice in [slice_first, slice_first+slice_count) at once, in
+ * place: x [slice_count][n], y [slice_count][n] (device, FP64). */
+int pr_chem_fine_propagate(const pr_chem *c, const pr_schedule *sched, uint64_t seed, uint32_t instance, int64_t n,
+                           int slice_first, int slice_count, double *x, double *y, void *stream);
+
+/* ybar (host): the mean of the fast variable's equilibrium density
+ * phi(y) ~ exp(int_0^y b(s)/E(s) ds)/E(y) (Sec. 2.2.1, the chemical
+ * reactions example), both integrals by the trapezoidal rule on the uniform
+ * grid of [0, 1000] with spacing 1e-2. */
+int pr_chem_mean_fast(const pr_chem *c, double *ybar);
+
+/* Coarse propagator of the chemical system: the finite-volume scheme of
+ * Sec. 2.2.2 for eq. (FPz) with Fbar'(x) = -(k4 ybar - k5 x) and
+ * Dbar(x) = (k4 ybar + k5 x)/2 (eq. (Fbar)/(Dbar) with phi independent of x),
+ * rho_inf(x) = exp(-int_0^x Fbar'/Dbar ds)/Dbar(x), edge coefficients
+ * Dbar(x_i) rho_inf(x_i)/(tau_x h), zero flux at the grid ends, advanced by
+ * E(tau) = exp(A tau) per distinct slice length.  Needs k4 ybar + k5 x_lo
+ * > 0.  The handle serves pr_coarse_fp_step, pr_coarse_matrix and
+ * pr_coarse_destroy like that of pr_coarse_create (synchronous). */
+int pr_chem_coarse_create(const pr_chem *c, const pr_schedule *sched, const pr_grid *grid, void *stream,
+                          void **coarse);
+
+/* Histogram-state parareal driver on the chemical system: as
+ * pr_parareal_hist_create, with the chemical fine propagator, initial law
+ * and coarse propagator (d = 1).  The handle is driven and released with the
+ * pr_parareal_hist_* calls. */
+int pr_parareal_hist_create_chem(const pr_chem *c, const pr_schedule *sched, const pr_grid *grid, uint64_t seed,
+                                 uint32_t instance, int64_t n, int iterator, int matching, int flags, void *stream,
+                                 void **h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,8 @@ __all__ = [
     "PR_M_RESAMPLE_DET", "pr_hist_workspace_size", "pr_hist_restrict", "pr_hist_jump_workspace_size", "pr_hist_jump",
     "pr_hist_match_workspace_size", "pr_hist_match", "pr_parareal_hist_create", "pr_parareal_hist_iterate",
     "pr_parareal_hist_state", "pr_parareal_hist_iteration", "pr_parareal_hist_profile", "pr_parareal_hist_destroy",
+    "Chem", "CHEM_K_DEFAULT", "pr_chem_init_ensemble", "pr_chem_fine_propagate", "pr_chem_mean_fast",
+    "pr_chem_coarse_create", "pr_parareal_hist_create_chem",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -87,6 +89,33 @@ class Grid:
         return _CGrid(self.n_cells, self.x_lo, self.x_hi, self.n_q)
 
 
+class _CChem(ctypes.Structure):
+    _fields_ = [("tau_x", _c_dbl), ("eps", _c_dbl), ("k", _c_dbl * 6), ("x0_mean", _c_dbl), ("x0_sd", _c_dbl),
+                ("y0_mean", _c_dbl), ("y0_sd", _c_dbl)]
+
+
+CHEM_K_DEFAULT = (60.0, 1.0, 4.8e-3, 0.666e-5, 0.833, 1.0)
+
+
+class Chem:
+    """Chemical-reaction system parameters (pr_chem): Table 1 defaults with
+    k3 = 0.666e-5 (bistable fast variable)."""
+
+    def __init__(self, tau_x=25.0, eps=2.5e-2, k=CHEM_K_DEFAULT, x0=(100.0, 20.0), y0=(100.0, 20.0)):
+        self.tau_x, self.eps = float(tau_x), float(eps)
+        self.k = tuple(float(v) for v in k)
+        self.x0, self.y0 = tuple(x0), tuple(y0)
+
+    def c(self):
+        s = _CChem()
+        s.tau_x, s.eps = self.tau_x, self.eps
+        for i in range(6):
+            s.k[i] = self.k[i]
+        s.x0_mean, s.x0_sd = self.x0
+        s.y0_mean, s.y0_sd = self.y0
+        return s
+
+
 class PrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"pr status {status}: {msg}")
@@ -147,6 +176,15 @@ _SIGS = {
     "pr_parareal_hist_iteration": (_c_int, [_vp]),
     "pr_parareal_hist_profile": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_int)]),
     "pr_parareal_hist_destroy": (_c_int, [_vp]),
+    "pr_chem_init_ensemble": (_c_int, [ctypes.POINTER(_CChem), _c_u64, _c_u32, _c_i64, _vp, _vp, _vp]),
+    "pr_chem_fine_propagate": (_c_int, [ctypes.POINTER(_CChem), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64,
+                                        _c_int, _c_int, _vp, _vp, _vp]),
+    "pr_chem_mean_fast": (_c_int, [ctypes.POINTER(_CChem), ctypes.POINTER(_c_dbl)]),
+    "pr_chem_coarse_create": (_c_int, [ctypes.POINTER(_CChem), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid),
+                                       _vp, ctypes.POINTER(_vp)]),
+    "pr_parareal_hist_create_chem": (_c_int, [ctypes.POINTER(_CChem), ctypes.POINTER(_CSchedule),
+                                              ctypes.POINTER(_CGrid), _c_u64, _c_u32, _c_i64, _c_int, _c_int, _c_int,
+                                              _vp, ctypes.POINTER(_vp)]),
 }
 
 
@@ -428,3 +466,37 @@ def pr_parareal_hist_profile(h):
 
 def pr_parareal_hist_destroy(h):
     _check(lib().pr_parareal_hist_destroy(h))
+
+
+def pr_chem_init_ensemble(chem, seed, instance, n, x, y, stream=None):
+    c = chem.c()
+    _check(lib().pr_chem_init_ensemble(ctypes.byref(c), seed, instance, n, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def pr_chem_fine_propagate(chem, sched, seed, instance, n, slice_first, slice_count, x, y, stream=None):
+    c, s = chem.c(), sched.c()
+    _check(lib().pr_chem_fine_propagate(ctypes.byref(c), ctypes.byref(s), seed, instance, n, slice_first, slice_count,
+                                        _ptr(x), _ptr(y), _stream(stream)))
+
+
+def pr_chem_mean_fast(chem):
+    c = chem.c()
+    v = _c_dbl(0.0)
+    _check(lib().pr_chem_mean_fast(ctypes.byref(c), ctypes.byref(v)))
+    return v.value
+
+
+def pr_chem_coarse_create(chem, sched, grid, stream=None):
+    c, s, g = chem.c(), sched.c(), grid.c()
+    h = _vp()
+    _check(lib().pr_chem_coarse_create(ctypes.byref(c), ctypes.byref(s), ctypes.byref(g), _stream(stream),
+                                       ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_hist_create_chem(chem, sched, grid, seed, instance, n, iterator, matching, flags=0, stream=None):
+    c, s, g = chem.c(), sched.c(), grid.c()
+    h = _vp()
+    _check(lib().pr_parareal_hist_create_chem(ctypes.byref(c), ctypes.byref(s), ctypes.byref(g), seed, instance, n,
+                                              iterator, matching, flags, _stream(stream), ctypes.byref(h)))
+    return h

@@ -1,0 +1,28 @@
+// Internal interface of the chemical-reaction system (Sec. 2.1.2): the fine
+// propagator, the initial law and the coarse propagator, for the
+// histogram-state driver; and the coarse constructor from a tridiagonal
+// generator that both coarse models share.
+#pragma once
+
+#include <vector>
+
+#include "pr_internal.hpp"
+
+namespace pr {
+
+int check_chem(const pr_chem *c);
+int chem_init_ensemble(const pr_chem *c, uint64_t seed, uint32_t inst, int64_t n, double *x, double *y,
+                       hipStream_t st);
+int chem_fine_propagate(const pr_chem *c, const pr_schedule *sch, uint64_t seed, uint32_t inst, int64_t n,
+                        int slice_first, int slice_count, const double *xi, const double *yi, double *x, double *y,
+                        hipStream_t st);
+int chem_mean_fast(const pr_chem *c, double *ybar);
+int chem_coarse_create(const pr_chem *c, const pr_schedule *sch, const pr_grid *grid, hipStream_t st, Coarse **out);
+
+// Coarse handle from the generator A (lo[i] = A[i][i-1], di[i] = A[i][i],
+// up[i] = A[i][i+1]): E(tau) for every distinct slice length of sch.
+int coarse_create_tridiag(const std::vector<double> &lo, const std::vector<double> &di,
+                          const std::vector<double> &up, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
+                          Coarse **out);
+
+}  // namespace pr

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <vector>
 
+#include "pr_chem.hpp"
 #include "pr_coarse_dev.hpp"
 #include "pr_internal.hpp"
 
@@ -256,10 +257,16 @@ int make_generator(const pr_sde *sde, const pr_grid *grid, std::vector<double> &
 
 int coarse_create(const pr_sde *sde, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
                   Coarse **out) {
-    const int I = grid->n_cells;
-    const double h = (grid->x_hi - grid->x_lo) / I;
     std::vector<double> lo, di, up;
     PR_CHECK(make_generator(sde, grid, lo, di, up, st));
+    return coarse_create_tridiag(lo, di, up, sch, grid, st, out);
+}
+
+int coarse_create_tridiag(const std::vector<double> &lo, const std::vector<double> &di,
+                          const std::vector<double> &up, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
+                          Coarse **out) {
+    const int I = grid->n_cells;
+    const double h = (grid->x_hi - grid->x_lo) / I;
     Coarse *c = new Coarse();
     c->g = GridDev{I, grid->n_q, grid->x_lo, h};
     c->n_slices = sch->n_slices;

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "pr_chem.hpp"
 #include "pr_coarse_dev.hpp"
 #include "pr_internal.hpp"
 
@@ -943,6 +944,8 @@ __global__ void hist_error_kernel(const double *__restrict__ rho, const double *
 }
 
 struct HistPR {
+    bool chem_model = false;  // the chemical-reaction system instead of sde
+    pr_chem chem{};
     pr_sde sde;
     pr_schedule sch;
     pr_grid grid;
@@ -1053,9 +1056,19 @@ static int hist_match_states(HistPR *h, const double *rho_t, const double *rho_p
     return hist_match(h->mkind, a, K, h->g, make_key(h->seed), h->inst, 1, h->mws, st);
 }
 
-int hist_parareal_create(const pr_sde *sde_in, const pr_schedule *sch, const pr_grid *grid, uint64_t seed,
-                         uint32_t inst, int64_t n, int jkind, int mkind, int flags, hipStream_t st, HistPR **out) {
+// Exactly one of sde_in and chem is non-NULL.
+int hist_parareal_create(const pr_sde *sde_in, const pr_chem *chem, const pr_schedule *sch, const pr_grid *grid,
+                         uint64_t seed, uint32_t inst, int64_t n, int jkind, int mkind, int flags, hipStream_t st,
+                         HistPR **out) {
     HistPR *h = new HistPR();
+    pr_sde one{};
+    one.d_fast = 1;
+    one.precision = PR_F64;
+    if (chem) {
+        h->chem_model = true;
+        h->chem = *chem;
+        sde_in = &one;
+    }
     h->sde = *sde_in;
     h->sch = *sch;
     h->grid = *grid;
@@ -1095,12 +1108,18 @@ int hist_parareal_create(const pr_sde *sde_in, const pr_schedule *sch, const pr_
     HPR_ALLOC(h->hws, hist_ws_bytes(K + 1, I));
     HPR_ALLOC(h->jws, hist_jump_ws_bytes(1, I));
     HPR_ALLOC(h->mws, hist_match_ws_bytes(n, K, I));
-    HPR_TRY(coarse_create(&h->sde, sch, grid, st, &h->coarse));
+    if (h->chem_model)
+        HPR_TRY(chem_coarse_create(&h->chem, sch, grid, st, &h->coarse));
+    else
+        HPR_TRY(coarse_create(&h->sde, sch, grid, st, &h->coarse));
     if (flags & PR_PROFILE)
         for (hipEvent_t &e : h->ev) HPR_TRY(hipEventCreate(&e) == hipSuccess ? PR_OK : PR_E_HIP);
 
     // initial ensemble (and equal weights) in slot 0 of every buffer
-    HPR_TRY(init_ensemble(&h->sde, seed, inst, n, h->xs(0, 0), h->ys(0, 0), st));
+    if (h->chem_model)
+        HPR_TRY(chem_init_ensemble(&h->chem, seed, inst, n, h->xs(0, 0), h->ys(0, 0), st));
+    else
+        HPR_TRY(init_ensemble(&h->sde, seed, inst, n, h->xs(0, 0), h->ys(0, 0), st));
     for (int b = 0; b < nbuf; ++b) {
         if (h->w[b]) {
             hipLaunchKernelGGL(fill_f64, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256), 0, st,
@@ -1138,8 +1157,12 @@ int hist_parareal_iterate(HistPR *h, int n_iter, const double *rho_ref, double *
         const int c = h->cur, nx = (c + 1) % (resample ? 3 : 2), sp = resample ? (c + 2) % 3 : -1;
         PR_CHECK(mark(0));
         // 1. fine: Xbar^{t+1} = F_t(X_k^t) into buffer nx; the weights ride along
-        PR_CHECK(fine_propagate(&h->sde, &h->sch, h->seed, h->inst, n, 0, K, h->xs(c, 0), h->ys(c, 0), h->xs(nx, 1),
-                                h->ys(nx, 1), st));
+        if (h->chem_model)
+            PR_CHECK(chem_fine_propagate(&h->chem, &h->sch, h->seed, h->inst, n, 0, K, h->xs(c, 0), h->ys(c, 0),
+                                         h->xs(nx, 1), h->ys(nx, 1), st));
+        else
+            PR_CHECK(fine_propagate(&h->sde, &h->sch, h->seed, h->inst, n, 0, K, h->xs(c, 0), h->ys(c, 0),
+                                    h->xs(nx, 1), h->ys(nx, 1), st));
         if (h->weighted) PR_CHECK(copy_d(h->wsl(nx, 1), h->wsl(c, 0), sizeof(double) * K * n, st));
         PR_CHECK(mark(1));
         // 2. restriction of the fine results
@@ -1279,8 +1302,28 @@ extern "C" int pr_parareal_hist_create(const pr_sde *sde, const pr_schedule *sch
     PR_REQUIRE(sched->n_slices <= 1023, "at most 1023 slices");
     PR_REQUIRE((flags & ~(PR_REUSE_COARSE | PR_PROFILE)) == 0, "flags other than PR_REUSE_COARSE and PR_PROFILE");
     HistPR *p = nullptr;
-    PR_CHECK(hist_parareal_create(sde, sched, grid, seed, instance, n, iterator, matching, flags, as_stream(stream),
-                                  &p));
+    PR_CHECK(hist_parareal_create(sde, nullptr, sched, grid, seed, instance, n, iterator, matching, flags,
+                                  as_stream(stream), &p));
+    *h = p;
+    return PR_OK;
+}
+
+extern "C" int pr_parareal_hist_create_chem(const pr_chem *c, const pr_schedule *sched, const pr_grid *grid,
+                                            uint64_t seed, uint32_t instance, int64_t n, int iterator, int matching,
+                                            int flags, void *stream, void **h) {
+    clear_error();
+    PR_CHECK(check_chem(c));
+    PR_CHECK(check_schedule(sched));
+    PR_CHECK(check_hist_grid(grid));
+    PR_REQUIRE(h != nullptr, "h must be non-NULL");
+    PR_REQUIRE(iterator >= PR_J_ADD && iterator <= PR_J_QUANTILE, "unknown iterator %d", iterator);
+    PR_REQUIRE(matching >= PR_M_MARGINAL && matching <= PR_M_RESAMPLE_DET, "unknown matching %d", matching);
+    PR_REQUIRE(n >= 1 && n <= 0xFFFFFFFFll, "n must be in [1, 2^32)");
+    PR_REQUIRE(sched->n_slices <= 1023, "at most 1023 slices");
+    PR_REQUIRE((flags & ~(PR_REUSE_COARSE | PR_PROFILE)) == 0, "flags other than PR_REUSE_COARSE and PR_PROFILE");
+    HistPR *p = nullptr;
+    PR_CHECK(hist_parareal_create(nullptr, c, sched, grid, seed, instance, n, iterator, matching, flags,
+                                  as_stream(stream), &p));
     *h = p;
     return PR_OK;
 }

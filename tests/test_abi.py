@@ -85,3 +85,31 @@ def test_validation_rejects_before_launch(lib):
     assert L.pr_match_quantiles(None, None, None, 10, 1, 100, None, None, 64, None) == -1
     # iterate on a NULL handle
     assert L.pr_parareal_iterate(None, 1, None, None, None) == -1
+
+
+def test_chem_validation_and_host_mean(lib):
+    """The chemical system's arguments are checked before any launch, and the
+    fast-variable mean (host code) agrees with the oracle's trapezoidal rule."""
+    from oracle import chem as OCH
+    L = lib
+    s = pr.Schedule(100, 4, 1e-3).c()
+    assert L.pr_chem_init_ensemble(None, 0, 0, 10, None, None, None) == -1
+    for bad in (pr.Chem(k=(60.0, 1.0, 4.8e-3, 0.666e-5, 0.833, 0.0)), pr.Chem(eps=-1.0),
+                pr.Chem(k=(60.0, -1.0, 4.8e-3, 0.666e-5, 0.833, 1.0)), pr.Chem(x0=(0.0, 1.0))):
+        c = bad.c()
+        assert L.pr_chem_fine_propagate(ctypes.byref(c), ctypes.byref(s), 0, 0, 10, 0, 1, None, None, None) == -1
+    c = pr.Chem().c()
+    assert L.pr_chem_fine_propagate(ctypes.byref(c), ctypes.byref(s), 0, 0, 10, 3, 2, None, None, None) == -1
+    h = ctypes.c_void_p()
+    g = pr.Grid(n_cells=2000, x_lo=0.0, x_hi=600.0).c()
+    assert L.pr_parareal_hist_create_chem(ctypes.byref(c), ctypes.byref(s), ctypes.byref(g), 0, 0, 10, 0, 0, 0, None,
+                                          ctypes.byref(h)) == -1
+    g = pr.Grid(n_cells=600, x_lo=-400.0, x_hi=600.0).c()  # Dbar < 0 at the left end
+    assert L.pr_chem_coarse_create(ctypes.byref(c), ctypes.byref(s), ctypes.byref(g), None, ctypes.byref(h)) == -1
+    for k in (OCH.K_DEFAULT, (60.0, 1.0, 0.0, 0.0, 0.833, 1.0), (30.0, 0.5, 2e-3, 1e-6, 1.0, 0.5)):
+        got = pr.pr_chem_mean_fast(pr.Chem(k=k))
+        ref = OCH.mean_fast(OCH.Chem(k=k))
+        assert abs(got - ref) < 1e-12 * abs(ref), (k, got, ref)
+    # E(y) <= 0 somewhere on [0, 1000] is an error, not a NaN
+    with pytest.raises(pr.PrError):
+        pr.pr_chem_mean_fast(pr.Chem(k=(0.0, 0.0, 4.8e-3, 0.0, 0.833, 1.0)))
