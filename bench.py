@@ -243,9 +243,84 @@ def hist_measure(torch, pr, w, n, K, S, dt):
         rest = ph["restrict_fine"] / 1e3
         out[f"{it}+{mt}"] = dict(ms_per_iteration=sum(v for k, v in ph.items() if k != "restrict_new"),
                                  phases_ms=ph, l2_error_at_T=float(err[0]), l2_error_max=float(err[1]),
-                                 restrict_fine_GBps=n * K * 8 / rest / 1e9)
+                                 restrict_fine_GBps=n * K * (16 if mt == "reweight" else 8) / rest / 1e9)
     return dict(workload="histogram states (1024 cells on [-3, 3]) of the large workload: P=2^20, 64 slices, "
                          "1e5 steps of dt=1e-4; iterator + matching per entry; errors after two iterations",
+                combos=out)
+
+
+# VALU instructions of one particle-step of the chemical-reaction fine kernel:
+# Philox 32, the Box-Muller logarithm and angle without its square root (31),
+# the drift and diffusion of the reaction network, two square roots of the
+# amplitude times -2 ln u and the update (35): the compiled two-particle loop
+# issues 197.
+CHEM_VALU_PER_STEP = 98
+
+
+def chem_measure(torch, pr):
+    """The paper's own workload (Sec. 6, Table 1): chemical-reaction system,
+    P = 1e5 particles, N = 20 slices of T = 40 (dt = 1e-3, 40000 steps),
+    grid [0, 600] with h = 1 (600 cells).  For every iterator x matching
+    combination, K = 20 iterations with the L2 error of the slow variable's
+    histogram after each one against a serial run with ten times the
+    particles (its first P particles are the parareal ensemble, so the error
+    of a serial P-particle run is the floor).  Device times from HIP events
+    recorded by the driver."""
+    its = dict(add=pr.PR_J_ADD, mult=pr.PR_J_MULT, rot=pr.PR_J_ROT, quantile=pr.PR_J_QUANTILE)
+    mts = dict(marginal=pr.PR_M_MARGINAL, reweight=pr.PR_M_REWEIGHT, resample=pr.PR_M_RESAMPLE,
+               resample_det=pr.PR_M_RESAMPLE_DET)
+    n, K, S, dt, I, seed = 100_000, 20, 40_000, 1e-3, 600, 0
+    nr = 10 * n
+    chem, sched = pr.Chem(), pr.Schedule(S, K, dt)
+    grid = pr.Grid(n_cells=I, x_lo=0.0, x_hi=600.0)
+    x = torch.empty(nr, dtype=torch.float64, device="cuda")
+    y = torch.empty(nr, dtype=torch.float64, device="cuda")
+    pr.pr_chem_init_ensemble(chem, seed, 0, nr, x, y)
+    ref = torch.empty((K + 1, I), dtype=torch.float64, device="cuda")
+    own = torch.empty((K + 1, I), dtype=torch.float64, device="cuda")
+    ws = torch.empty(pr.pr_hist_workspace_size(1, I), dtype=torch.uint8, device="cuda")
+    pr.pr_hist_restrict(x, None, nr, 1, grid, ref[0], ws)
+    pr.pr_hist_restrict(x, None, n, 1, grid, own[0], ws)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    serial_ms = 0.0
+    for s_ in range(K):
+        ev[0].record()
+        pr.pr_chem_fine_propagate(chem, sched, seed, 0, nr, s_, 1, x, y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        serial_ms += ev[0].elapsed_time(ev[1])
+        pr.pr_hist_restrict(x, None, nr, 1, grid, ref[s_ + 1], ws)
+        pr.pr_hist_restrict(x, None, n, 1, grid, own[s_ + 1], ws)
+    floor = torch.sqrt(((own - ref) ** 2).sum(dim=1)).cpu().numpy()
+    del x, y
+    out = {}
+    fine_ms = []
+    for it in its:
+        for mt in mts:
+            log(f"chemical {it}+{mt}")
+            h = pr.pr_parareal_hist_create_chem(chem, sched, grid, seed, 0, n, its[it], mts[mt], flags=pr.PR_PROFILE)
+            try:
+                err = np.zeros(2 * K)
+                pr.pr_parareal_hist_iterate(h, K, rho_ref=ref, err_out=err)
+                ph, iters = pr.pr_parareal_hist_profile(h)
+            finally:
+                pr.pr_parareal_hist_destroy(h)
+            ph = {k: v / iters for k, v in ph.items()}
+            fine_ms.append(ph["fine"])
+            out[f"{it}+{mt}"] = dict(
+                ms_per_iteration=sum(v for k, v in ph.items() if k != "restrict_new"), phases_ms=ph,
+                l2_error_at_T=[float("%.4g" % e) for e in err[0::2]],
+                l2_error_max=[float("%.4g" % e) for e in err[1::2]])
+    fine = float(np.median(fine_ms))
+    rate = n * S / (fine / 1e3)
+    return dict(workload="chemical-reaction system (Table 1: tau_x=25, eps=2.5e-2, k=(60, 1, 4.8e-3, 0.666e-5, "
+                         "0.833, 1)), lognormal X0, Y0 (mean 100, sd 20), P=1e5, N=20, T=40, dt=1e-3, "
+                         "600 cells on [0, 600]; K=20 iterations per iterator + matching; L2 histogram errors "
+                         "after each iteration against a serial run with 1e6 particles",
+                fine_ms=fine, fine_particle_steps_per_s=rate,
+                fine_valu_frac=CHEM_VALU_PER_STEP * rate / VALU_PEAK,
+                serial_fine_ms_1e6_particles=serial_ms,
+                floor_l2_error_serial_1e5=[float("%.4g" % e) for e in floor],
                 combos=out)
 
 
@@ -385,6 +460,8 @@ def main():
     out["high_dim"] = highdim_measure(torch, pr)
     log("histogram states")
     out["hist_states"] = hist_measure(torch, pr, w, n, K, S, dt)
+    log("chemical-reaction workload")
+    out["chemical"] = chem_measure(torch, pr)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -5,6 +5,9 @@ that rocprofv3 counter passes cover a handful of dispatches.
     python -m paper_1912_09240_amd.profile_workload restrict  # sort of 64 x 2^20 keys with ranks
     python -m paper_1912_09240_amd.profile_workload match     # matching of 64 x 2^20 particles
     python -m paper_1912_09240_amd.profile_workload copy      # device-to-device copy of 1 GiB
+    python -m paper_1912_09240_amd.profile_workload hist      # histograms, marginal matching and
+                                                              # stratified resampling, 64 x 2^20
+    python -m paper_1912_09240_amd.profile_workload chem      # chemical-reaction fine launch (Table 1)
 
 Large workload: lambda = 1, beta = 2, eps = 0.01, P = 2^20, dt = 1e-4, T = 10
 (1e5 steps) in 64 slices, 100 quantile levels; the slice states start from
@@ -66,7 +69,44 @@ def copy():
         torch.cuda.synchronize()
 
 
+def hist():
+    """Histogram restriction of the 64 ensembles (1024 cells on [-3, 3]),
+    then the fast-marginal matching and the stratified resampling of every
+    ensemble against its histogram shifted by five cells."""
+    _, x, y = _ensemble()
+    grid = pr.Grid(n_cells=1024)
+    ws = torch.empty(pr.pr_hist_workspace_size(K, 1024), dtype=torch.uint8, device="cuda")
+    rho = torch.empty((K, 1024), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        pr.pr_hist_restrict(x, None, N, K, grid, rho, ws)
+        torch.cuda.synchronize()
+    rt = torch.roll(rho, 5, dims=1).contiguous()
+    mws = torch.empty(pr.pr_hist_match_workspace_size(N, K, 1024), dtype=torch.uint8, device="cuda")
+    xo, yo, wo = torch.empty_like(x), torch.empty_like(y), torch.empty_like(x)
+    for kind in (pr.PR_M_MARGINAL, pr.PR_M_RESAMPLE):
+        for _ in range(2):
+            pr.pr_hist_match(kind, rt, rho, N, K, 1, grid, x, y, None, N, xo, yo, wo, mws, seed=0, instance=0,
+                             t_first=1)
+            torch.cuda.synchronize()
+
+
+def chem():
+    """The chemical-reaction fine propagator on the workload of Table 1:
+    P = 1e5, N = 20 slices of T = 40 (dt = 1e-3), all slices in one launch."""
+    n, k, s_total, dt = 100_000, 20, 40_000, 1e-3
+    c = pr.Chem()
+    x0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    y0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    pr.pr_chem_init_ensemble(c, 0, 0, n, x0, y0)
+    x, y = x0.repeat(k, 1).contiguous(), y0.repeat(k, 1).contiguous()
+    sched = pr.Schedule(s_total, k, dt)
+    for _ in range(2):
+        xs, ys = x.clone(), y.clone()
+        pr.pr_chem_fine_propagate(c, sched, 0, 0, n, 0, k, xs, ys)
+        torch.cuda.synchronize()
+
+
 if __name__ == "__main__":
     group = sys.argv[1] if len(sys.argv) > 1 else "fine"
-    {"fine": fine, "restrict": restrict, "match": match, "copy": copy}[group]()
+    {"fine": fine, "restrict": restrict, "match": match, "copy": copy, "hist": hist, "chem": chem}[group]()
     print(f"profile_workload {group}: done", flush=True)
