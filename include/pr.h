@@ -443,6 +443,40 @@ int pr_parareal_hist_create_chem(const pr_chem *c, const pr_schedule *sched, con
                                  uint32_t instance, int64_t n, int iterator, int matching, int flags, void *stream,
                                  void **h);
 
+/*
+ * Linear-advection study (Sec. 6, the linear advection case): the slow
+ * Fokker-Planck equation eq. (FPz) with Fbar(x) = x/eps and Dbar = 1/beta
+ * (tau_x = 1), discretised by the finite-volume scheme of Sec. 2.2.2 with
+ * rho_inf(x) ~ exp(-beta x/eps) and zero flux at the grid ends, advanced by
+ * E(tau) = exp(A tau) per distinct slice length.  eps, beta > 0.  The handle
+ * serves pr_coarse_fp_step, pr_coarse_matrix, pr_coarse_destroy and the
+ * deterministic parareal below (synchronous).
+ */
+int pr_advection_coarse_create(double eps, double beta, const pr_schedule *sched, const pr_grid *grid,
+                               void *stream, void **coarse);
+
+/*
+ * Deterministic parareal on cell masses (Sec. 6, the linear advection case):
+ * the fine and the coarse propagator are two coarse handles (any model) of
+ * the same grid and slice count, each applying its E once per slice with
+ * negative rounding residue clipped to 0; restriction and matching are the
+ * identity; the iterator is one of PR_J_* (as in pr_hist_jump).  create
+ * copies rho0 (device, [I]) and runs the zeroth iteration
+ * rho^{n+1} = C_n(rho^n); iterate runs n_iter iterations
+ * rho_{k+1}^{n+1} = J(C_n(rho_{k+1}^n), F_n(rho_k^n), C_n(rho_k^n)), the fine
+ * and coarse propagation of all slices in one batched launch each and the
+ * serial chain one link per slice.  With rho_ref (device, [N+1][I]),
+ * err_out (host, [n_iter][2]) receives after each iteration the L2 error at
+ * n = N and its maximum over n.  The handles must outlive the parareal
+ * handle.  flags: 0.
+ */
+int pr_parareal_fp_create(const void *fine, const void *coarse, const pr_grid *grid, const double *rho0,
+                          int iterator, int flags, void *stream, void **h);
+int pr_parareal_fp_iterate(void *h, int n_iter, const double *rho_ref, double *err_out, void *stream);
+int pr_parareal_fp_state(void *h, int t, double *rho, void *stream);
+int pr_parareal_fp_iteration(const void *h);
+int pr_parareal_fp_destroy(void *h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ __all__ = [
     "pr_hist_match_workspace_size", "pr_hist_match", "pr_parareal_hist_create", "pr_parareal_hist_iterate",
     "pr_parareal_hist_state", "pr_parareal_hist_iteration", "pr_parareal_hist_profile", "pr_parareal_hist_destroy",
     "Chem", "CHEM_K_DEFAULT", "pr_chem_init_ensemble", "pr_chem_fine_propagate", "pr_chem_mean_fast",
-    "pr_chem_coarse_create", "pr_parareal_hist_create_chem",
+    "pr_chem_coarse_create", "pr_parareal_hist_create_chem", "pr_advection_coarse_create", "pr_parareal_fp_create",
+    "pr_parareal_fp_iterate", "pr_parareal_fp_state", "pr_parareal_fp_iteration", "pr_parareal_fp_destroy",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -185,6 +186,14 @@ _SIGS = {
     "pr_parareal_hist_create_chem": (_c_int, [ctypes.POINTER(_CChem), ctypes.POINTER(_CSchedule),
                                               ctypes.POINTER(_CGrid), _c_u64, _c_u32, _c_i64, _c_int, _c_int, _c_int,
                                               _vp, ctypes.POINTER(_vp)]),
+    "pr_advection_coarse_create": (_c_int, [_c_dbl, _c_dbl, ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid), _vp,
+                                            ctypes.POINTER(_vp)]),
+    "pr_parareal_fp_create": (_c_int, [_vp, _vp, ctypes.POINTER(_CGrid), _vp, _c_int, _c_int, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "pr_parareal_fp_iterate": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
+    "pr_parareal_fp_state": (_c_int, [_vp, _c_int, _vp, _vp]),
+    "pr_parareal_fp_iteration": (_c_int, [_vp]),
+    "pr_parareal_fp_destroy": (_c_int, [_vp]),
 }
 
 
@@ -500,3 +509,38 @@ def pr_parareal_hist_create_chem(chem, sched, grid, seed, instance, n, iterator,
     _check(lib().pr_parareal_hist_create_chem(ctypes.byref(c), ctypes.byref(s), ctypes.byref(g), seed, instance, n,
                                               iterator, matching, flags, _stream(stream), ctypes.byref(h)))
     return h
+
+
+def pr_advection_coarse_create(eps, beta, sched, grid, stream=None):
+    s, g = sched.c(), grid.c()
+    h = _vp()
+    _check(lib().pr_advection_coarse_create(eps, beta, ctypes.byref(s), ctypes.byref(g), _stream(stream),
+                                            ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_fp_create(fine, coarse, grid, rho0, iterator, flags=0, stream=None):
+    g = grid.c()
+    h = _vp()
+    _check(lib().pr_parareal_fp_create(fine, coarse, ctypes.byref(g), _ptr(rho0), iterator, flags, _stream(stream),
+                                       ctypes.byref(h)))
+    return h
+
+
+def pr_parareal_fp_iterate(h, n_iter, rho_ref=None, err_out=None, stream=None):
+    """err_out: host float64 numpy array of 2 * n_iter (error at N, max over n)."""
+    _check(lib().pr_parareal_fp_iterate(h, n_iter, _ptr(rho_ref),
+                                        err_out.ctypes.data_as(_vp) if err_out is not None else None,
+                                        _stream(stream)))
+
+
+def pr_parareal_fp_state(h, t, rho, stream=None):
+    _check(lib().pr_parareal_fp_state(h, t, _ptr(rho), _stream(stream)))
+
+
+def pr_parareal_fp_iteration(h):
+    return lib().pr_parareal_fp_iteration(h)
+
+
+def pr_parareal_fp_destroy(h):
+    _check(lib().pr_parareal_fp_destroy(h))

@@ -1,7 +1,7 @@
-// Internal interface of the chemical-reaction system (Sec. 2.1.2): the fine
-// propagator, the initial law and the coarse propagator, for the
-// histogram-state driver; and the coarse constructor from a tridiagonal
-// generator that both coarse models share.
+// Internal interface of the models beside the double-well SDE: the
+// chemical-reaction system (Sec. 2.1.2: fine propagator, initial law, coarse
+// propagator) and the linear-advection coarse model (Sec. 6); and the coarse
+// constructor from a tridiagonal generator that every coarse model shares.
 #pragma once
 
 #include <vector>
@@ -18,6 +18,11 @@ int chem_fine_propagate(const pr_chem *c, const pr_schedule *sch, uint64_t seed,
                         hipStream_t st);
 int chem_mean_fast(const pr_chem *c, double *ybar);
 int chem_coarse_create(const pr_chem *c, const pr_schedule *sch, const pr_grid *grid, hipStream_t st, Coarse **out);
+
+int advection_coarse_create(double eps, double beta, const pr_schedule *sch, const pr_grid *grid, hipStream_t st,
+                            Coarse **out);
+int coarse_n_slices(const Coarse *c);
+int coarse_grid_cells(const Coarse *c);
 
 // Coarse handle from the generator A (lo[i] = A[i][i-1], di[i] = A[i][i],
 // up[i] = A[i][i+1]): E(tau) for every distinct slice length of sch.

@@ -372,6 +372,7 @@ int coarse_apply(const Coarse *c, int first, int count, const double *rho_in, do
 }
 
 int coarse_grid_nq(const Coarse *c) { return c->g.nq; }
+int coarse_n_slices(const Coarse *c) { return c->n_slices; }
 int coarse_grid_cells(const Coarse *c) { return c->g.cells; }
 
 void coarse_free(Coarse *c) {

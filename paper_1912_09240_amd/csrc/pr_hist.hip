@@ -1218,6 +1218,87 @@ int hist_parareal_iterate(HistPR *h, int n_iter, const double *rho_ref, double *
     return PR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic parareal on cell masses (the linear-advection study): F and C
+// are two coarse handles, restriction and matching the identity.
+// ---------------------------------------------------------------------------
+struct FpPR {
+    const Coarse *fine = nullptr, *coarse = nullptr;
+    HGrid g;
+    int K = 0, I = 0, jkind = 0, k = 0;
+    double *rho = nullptr, *rho_new = nullptr;  // [K+1][I]
+    double *rho_f = nullptr, *rho_cs = nullptr; // [K+1][I], rows 1..K used
+    double *rho_c = nullptr;                    // [I]
+    double *err = nullptr;                      // [2]
+    void *jws = nullptr;
+    double *row(double *b, int t) const { return b + (size_t)t * I; }
+};
+
+static void fp_free(FpPR *h) {
+    if (!h) return;
+    void *ptrs[] = {h->rho, h->rho_new, h->rho_f, h->rho_cs, h->rho_c, h->err, h->jws};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete h;
+}
+
+int fp_parareal_create(const Coarse *fine, const Coarse *coarse, const pr_grid *grid, const double *rho0, int jkind,
+                       hipStream_t st, FpPR **out) {
+    FpPR *h = new FpPR();
+    h->fine = fine;
+    h->coarse = coarse;
+    h->g = make_hgrid(grid);
+    h->K = coarse_n_slices(coarse);
+    h->I = grid->n_cells;
+    h->jkind = jkind;
+    const size_t rb = sizeof(double) * (size_t)(h->K + 1) * h->I;
+    auto fail = [&](int code, const char *what) {
+        set_error("%s", what);
+        fp_free(h);
+        return code;
+    };
+    if (hipMalloc(&h->rho, rb) != hipSuccess || hipMalloc(&h->rho_new, rb) != hipSuccess ||
+        hipMalloc(&h->rho_f, rb) != hipSuccess || hipMalloc(&h->rho_cs, rb) != hipSuccess ||
+        hipMalloc(&h->rho_c, sizeof(double) * h->I) != hipSuccess || hipMalloc(&h->err, 2 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->jws, hist_jump_ws_bytes(1, h->I)) != hipSuccess)
+        return fail(PR_E_NOMEM, "device allocation of the parareal state failed");
+    if (copy_d(h->rho, rho0, sizeof(double) * h->I, st) != PR_OK) return fail(PR_E_HIP, "copy of rho0 failed");
+    for (int t = 0; t < h->K; ++t)
+        if (coarse_apply(coarse, t, 1, h->row(h->rho, t), h->row(h->rho, t + 1), st) != PR_OK)
+            return fail(PR_E_HIP, "zeroth iteration failed");
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(PR_E_HIP, "zeroth iteration failed on the device");
+    *out = h;
+    return PR_OK;
+}
+
+int fp_parareal_iterate(FpPR *h, int n_iter, const double *rho_ref, double *err_out, hipStream_t st) {
+    const int K = h->K, I = h->I;
+    for (int it = 0; it < n_iter; ++it) {
+        // fine and coarse propagation of the current states, all slices at once
+        PR_CHECK(coarse_apply(h->fine, 0, K, h->rho, h->row(h->rho_f, 1), st));
+        PR_CHECK(coarse_apply(h->coarse, 0, K, h->rho, h->row(h->rho_cs, 1), st));
+        // serial chain
+        PR_CHECK(copy_d(h->rho_new, h->rho, sizeof(double) * I, st));
+        for (int t = 0; t < K; ++t) {
+            PR_CHECK(coarse_apply(h->coarse, t, 1, h->row(h->rho_new, t), h->rho_c, st));
+            PR_CHECK(hist_jump_launch(h->jkind, h->rho_c, h->row(h->rho_f, t + 1), h->row(h->rho_cs, t + 1), 0, 1,
+                                      h->row(h->rho_new, t + 1), 0, h->g, (double *)h->jws, st));
+        }
+        std::swap(h->rho, h->rho_new);
+        h->k += 1;
+        if (rho_ref) {
+            hipLaunchKernelGGL(hist_error_kernel, dim3(1), dim3(256), 0, st, (const double *)h->rho, rho_ref, K, I,
+                               h->err);
+            PR_LAUNCHED();
+            if (err_out) {
+                PR_HIP(hipMemcpyAsync(err_out + 2 * it, h->err, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+                PR_HIP(hipStreamSynchronize(st));
+            }
+        }
+    }
+    return PR_OK;
+}
+
 }  // namespace pr
 
 using namespace pr;
@@ -1374,6 +1455,51 @@ extern "C" int pr_parareal_hist_destroy(void *h) {
     if (h) {
         (void)hipDeviceSynchronize();
         hist_free((HistPR *)h);
+    }
+    return PR_OK;
+}
+
+extern "C" int pr_parareal_fp_create(const void *fine, const void *coarse, const pr_grid *grid, const double *rho0,
+                                     int iterator, int flags, void *stream, void **h) {
+    clear_error();
+    PR_CHECK(check_hist_grid(grid));
+    PR_REQUIRE(fine != nullptr && coarse != nullptr && rho0 != nullptr && h != nullptr,
+               "fine, coarse, rho0 and h must be non-NULL");
+    PR_REQUIRE(iterator >= PR_J_ADD && iterator <= PR_J_QUANTILE, "unknown iterator %d", iterator);
+    PR_REQUIRE(flags == 0, "no flags are defined for this driver");
+    const Coarse *f = (const Coarse *)fine, *c = (const Coarse *)coarse;
+    PR_REQUIRE(coarse_grid_cells(f) == grid->n_cells && coarse_grid_cells(c) == grid->n_cells,
+               "both propagators must use the %d cells of the grid", grid->n_cells);
+    PR_REQUIRE(coarse_n_slices(f) == coarse_n_slices(c), "fine and coarse propagators need the same slices");
+    PR_REQUIRE(coarse_n_slices(c) <= 1023, "at most 1023 slices");
+    FpPR *p = nullptr;
+    PR_CHECK(fp_parareal_create(f, c, grid, rho0, iterator, as_stream(stream), &p));
+    *h = p;
+    return PR_OK;
+}
+
+extern "C" int pr_parareal_fp_iterate(void *h, int n_iter, const double *rho_ref, double *err_out, void *stream) {
+    clear_error();
+    PR_REQUIRE(h != nullptr && n_iter >= 0, "need a handle and n_iter >= 0");
+    PR_REQUIRE(err_out == nullptr || rho_ref != nullptr, "err_out needs rho_ref");
+    return fp_parareal_iterate((FpPR *)h, n_iter, rho_ref, err_out, as_stream(stream));
+}
+
+extern "C" int pr_parareal_fp_state(void *hv, int t, double *rho, void *stream) {
+    clear_error();
+    FpPR *h = (FpPR *)hv;
+    PR_REQUIRE(h != nullptr && rho != nullptr, "need a handle and rho");
+    PR_REQUIRE(t >= 0 && t <= h->K, "t must be in [0, %d]", h->K);
+    return copy_d(rho, h->row(h->rho, t), sizeof(double) * h->I, as_stream(stream));
+}
+
+extern "C" int pr_parareal_fp_iteration(const void *h) { return h ? ((const FpPR *)h)->k : -1; }
+
+extern "C" int pr_parareal_fp_destroy(void *h) {
+    clear_error();
+    if (h) {
+        (void)hipDeviceSynchronize();
+        fp_free((FpPR *)h);
     }
     return PR_OK;
 }

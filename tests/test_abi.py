@@ -113,3 +113,14 @@ def test_chem_validation_and_host_mean(lib):
     # E(y) <= 0 somewhere on [0, 1000] is an error, not a NaN
     with pytest.raises(pr.PrError):
         pr.pr_chem_mean_fast(pr.Chem(k=(0.0, 0.0, 4.8e-3, 0.0, 0.833, 1.0)))
+
+
+def test_advection_validation(lib):
+    L = lib
+    s, g = pr.Schedule(100, 4, 1e-2).c(), pr.Grid(n_cells=100, x_lo=-8.0, x_hi=8.0).c()
+    h = ctypes.c_void_p()
+    assert L.pr_advection_coarse_create(0.0, 1.0, ctypes.byref(s), ctypes.byref(g), None, ctypes.byref(h)) == -1
+    assert L.pr_advection_coarse_create(1.0, -1.0, ctypes.byref(s), ctypes.byref(g), None, ctypes.byref(h)) == -1
+    assert L.pr_parareal_fp_create(None, None, ctypes.byref(g), None, 0, 0, None, ctypes.byref(h)) == -1
+    assert L.pr_parareal_fp_iterate(None, 1, None, None, None) == -1
+    assert L.pr_parareal_fp_iteration(None) == -1
