@@ -324,6 +324,66 @@ def chem_measure(torch, pr):
                 combos=out)
 
 
+def advection_measure(torch, pr):
+    """Linear-advection study (Sec. 6): fine model Fbar = x, Dbar = 1 on 800
+    cells of [-8, 8], X0 ~ N(2, 1/4), T = 1 in N = 10 slices; coarse models
+    with beta~ = 2 (underdiffusive), eps~ = 2 (wrong advection speed) and
+    beta~ = 1/2 (overdiffusive).  For every iterator: the L2 error of the
+    masses at T against the serial fine run after k = 0..5 iterations, and
+    the device time of one iteration."""
+    import scipy.stats as st
+    I, K, T = 800, 10, 1.0
+    grid = pr.Grid(n_cells=I, x_lo=-8.0, x_hi=8.0)
+    sched = pr.Schedule(100 * K, K, T / (100 * K))
+    edges = np.linspace(-8.0, 8.0, I + 1)
+    c = st.norm.cdf(edges, loc=2.0, scale=0.5)
+    r0 = np.diff(c)
+    r0[0] += c[0]
+    r0[-1] += 1.0 - c[-1]
+    rho0 = torch.from_numpy(r0).cuda()
+    its = dict(add=pr.PR_J_ADD, mult=pr.PR_J_MULT, rot=pr.PR_J_ROT, quantile=pr.PR_J_QUANTILE)
+    hf = pr.pr_advection_coarse_create(1.0, 1.0, sched, grid)
+    ref = torch.empty((K + 1, I), dtype=torch.float64, device="cuda")
+    ref[0] = rho0
+    out = {}
+    try:
+        # the serial fine run through the fine model's own exponentials
+        hs = pr.pr_parareal_fp_create(hf, hf, grid, rho0, pr.PR_J_ADD)
+        try:
+            for t in range(K + 1):
+                pr.pr_parareal_fp_state(hs, t, ref[t])
+        finally:
+            pr.pr_parareal_fp_destroy(hs)
+        for name, (ec, bc) in dict(underdiffusive=(1.0, 2.0), advection=(2.0, 1.0),
+                                    overdiffusive=(1.0, 0.5)).items():
+            hc = pr.pr_advection_coarse_create(ec, bc, sched, grid)
+            try:
+                row = {}
+                for it, kind in its.items():
+                    h = pr.pr_parareal_fp_create(hf, hc, grid, rho0, kind)
+                    try:
+                        rho = torch.empty(I, dtype=torch.float64, device="cuda")
+                        pr.pr_parareal_fp_state(h, K, rho)
+                        errs = [float(torch.sqrt(((rho - ref[K]) ** 2).sum()))]
+                        e = np.zeros(2 * 5)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        pr.pr_parareal_fp_iterate(h, 5, rho_ref=ref, err_out=e)
+                        ms = (time.perf_counter() - t0) * 1e3 / 5
+                        errs += [float(v) for v in e[0::2]]
+                    finally:
+                        pr.pr_parareal_fp_destroy(h)
+                    row[it] = dict(l2_error_at_T=[float("%.3g" % v) for v in errs], ms_per_iteration=ms)
+                out[name] = dict(coarse=dict(eps=ec, beta=bc), iterators=row)
+            finally:
+                pr.pr_coarse_destroy(hc)
+    finally:
+        pr.pr_coarse_destroy(hf)
+    return dict(workload="linear advection: Fbar = x/eps, Dbar = 1/beta, eps = beta = 1, 800 cells on [-8, 8], "
+                         "X0 ~ N(2, 1/4), T = 1, N = 10; errors after k = 0..5 iterations",
+                models=out)
+
+
 def highdim_measure(torch, pr):
     """Fast part in R^32 (dY_i = -(1/eps)(Y_i - a_i X) dt + ..., a_i from the
     seed): one fine sweep of all 32 slices (P = 2^20, 5e4 steps of 1e-4) in
@@ -462,6 +522,8 @@ def main():
     out["hist_states"] = hist_measure(torch, pr, w, n, K, S, dt)
     log("chemical-reaction workload")
     out["chemical"] = chem_measure(torch, pr)
+    log("linear advection")
+    out["advection"] = advection_measure(torch, pr)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
