@@ -185,7 +185,8 @@ __global__ void __launch_bounds__(256) chain_kernel(const ChainInst *__restrict_
     double *rho2 = rho + g.cells;   // cells
     double *C = rho2 + g.cells;     // cells + 1
     double *S = C + g.cells + 1;    // Q1
-    int *Cn = (int *)(S + Q1);      // Q1
+    int *SC = (int *)(S + Q1);      // Q1
+    int *vio = SC + Q1;             // Q1
     const ChainInst I = ci[inst0 + blockIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int j = threadIdx.x; j < Q1; j += blockDim.x) {
@@ -213,8 +214,7 @@ __global__ void __launch_bounds__(256) chain_kernel(const ChainInst *__restrict_
         if (qf) {
             for (int j = threadIdx.x; j < Q1; j += blockDim.x) qc[j] = qf[orow + j] + (qc[j] - qcs[orow + j]);
             __syncthreads();
-            if (threadIdx.x == 0) pava_serial(qc, Q1, S, Cn);
-            __syncthreads();
+            pava_block(qc, Q1, S, SC, vio);
         }
         for (int j = threadIdx.x; j < Q1; j += blockDim.x) qn[orow + j] = qc[j];
         __syncthreads();
@@ -361,7 +361,7 @@ static int upload(T *&dev, const std::vector<T> &h, hipStream_t st) {
 }
 
 static size_t lds_chain(const GridDev &g) {
-    return sizeof(double) * (2 * (g.nq + 1) + 4 * g.cells + 2) + sizeof(int) * (g.nq + 1);
+    return sizeof(double) * (2 * (g.nq + 1) + 4 * g.cells + 2) + 2 * sizeof(int) * (g.nq + 1);
 }
 
 // Fine units of a given tile size, in decreasing cost.

@@ -100,6 +100,36 @@ __global__ void __launch_bounds__(256) knots_to_masses(const double *__restrict_
     }
 }
 
+// One chain link's coarse step without the masses in global memory: every
+// block turns the knots q into the cell masses (the arithmetic of
+// knots_to_masses) in LDS and forms its four rows of max(E rho, 0).
+__global__ void __launch_bounds__(256) apply_expm_knots(const double *__restrict__ E, const int *__restrict__ tau_id,
+                                                        int slice, const double *__restrict__ q,
+                                                        double *__restrict__ rout, GridDev g) {
+#pragma clang fp contract(off)
+    extern __shared__ double sh[];
+    const int n = g.cells;
+    double *qs = sh;            // nq + 1
+    double *c = qs + g.nq + 1;  // cells + 1
+    double *rv = c + n + 1;     // cells
+    for (int j = threadIdx.x; j <= g.nq; j += blockDim.x) qs[j] = q[j];
+    __syncthreads();
+    for (int i = 1 + threadIdx.x; i < n; i += blockDim.x) c[i] = cdf_knots(qs, g.nq, edge_at(g, i));
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        rv[i] = (i == 0) ? c[1] : (i == n - 1) ? 1.0 - c[n - 1] : c[i + 1] - c[i];
+    __syncthreads();
+    const double *Es = E + (int64_t)tau_id[slice] * n * n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + wave;
+    if (r >= n) return;
+    const double *row = Es + (int64_t)r * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc = fma(row[j], rv[j], acc);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) rout[r] = acc > 0.0 ? acc : 0.0;
+}
+
 // rho_out[s] = max(E_{id(s)} rho_in[s], 0).  One wave per row.
 __global__ void __launch_bounds__(256) apply_expm(const double *__restrict__ E, const int *__restrict__ tau_id,
                                                   int slice_first, const double *__restrict__ rin,
@@ -141,7 +171,8 @@ __global__ void __launch_bounds__(256) qf_and_jump(const double *__restrict__ rh
     double *C = r + g.cells;
     double *qc = C + g.cells + 1;
     double *S = qc + g.nq + 1;
-    int *Cn = (int *)(S + g.nq + 1);
+    int *SC = (int *)(S + g.nq + 1);
+    int *vio = SC + g.nq + 1;
     for (int i = threadIdx.x; i < g.cells; i += blockDim.x) r[i] = rho[i];
     __syncthreads();
     masses_to_knots_block(r, C, g, qc);
@@ -151,8 +182,7 @@ __global__ void __launch_bounds__(256) qf_and_jump(const double *__restrict__ rh
         qc[j] = qf[j] + (qc[j] - qcs[j]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) pava_serial(qc, g.nq + 1, S, Cn);
-    __syncthreads();
+    pava_block(qc, g.nq + 1, S, SC, vio);
     for (int j = threadIdx.x; j <= g.nq; j += blockDim.x) q_out[j] = qc[j];
 }
 
@@ -326,7 +356,7 @@ int coarse_create_tridiag(const std::vector<double> &lo, const std::vector<doubl
 static size_t lds_knots_to_masses(const GridDev &g) { return sizeof(double) * (g.nq + 1 + g.cells + 1); }
 static size_t lds_masses_to_knots(const GridDev &g) { return sizeof(double) * (2 * g.cells + 1); }
 static size_t lds_qf_jump(const GridDev &g) {
-    return sizeof(double) * (2 * g.cells + 1 + 2 * (g.nq + 1)) + sizeof(int) * (g.nq + 1);
+    return sizeof(double) * (2 * g.cells + 1 + 2 * (g.nq + 1)) + 2 * sizeof(int) * (g.nq + 1);
 }
 
 // Batched coarse step of slices [first, first+count): q_in -> q_out.
@@ -350,10 +380,9 @@ int coarse_step(const Coarse *c, int first, int count, const double *q_in, int i
 int coarse_jump(const Coarse *c, int n, const double *q_cur, const double *qf, const double *qcs, double *q_next,
                 double *qc_out, hipStream_t st) {
     const GridDev &g = c->g;
-    hipLaunchKernelGGL(knots_to_masses, dim3(1), dim3(256), lds_knots_to_masses(g), st, q_cur, 0, c->rho_a, g);
-    PR_LAUNCHED();
-    hipLaunchKernelGGL(apply_expm, dim3((g.cells + 3) / 4, 1), dim3(256), sizeof(double) * g.cells, st,
-                       (const double *)c->E, (const int *)c->tau_id, n, (const double *)c->rho_a, c->rho_b, g.cells);
+    hipLaunchKernelGGL(apply_expm_knots, dim3((g.cells + 3) / 4), dim3(256),
+                       sizeof(double) * (g.nq + 1 + 2 * g.cells + 1), st, (const double *)c->E,
+                       (const int *)c->tau_id, n, q_cur, c->rho_b, g);
     PR_LAUNCHED();
     hipLaunchKernelGGL(qf_and_jump, dim3(1), dim3(256), lds_qf_jump(g), st, (const double *)c->rho_b, qf, qcs, q_next,
                        qc_out, g);

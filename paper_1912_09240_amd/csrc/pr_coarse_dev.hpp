@@ -115,27 +115,113 @@ __device__ inline void masses_to_knots_block(const double *rho, double *C, const
     }
 }
 
-// Pool-adjacent-violators (equal weights), single thread, in place; L <= cap.
-__device__ inline void pava_serial(double *v, int L, double *S, int *Cn) {
+// Pool-adjacent-violators (equal weights) with the same additions, divisions
+// and comparisons as the textbook stack form: a new value starts a pool (sum
+// s, count c); while the pool below has a larger mean S/C it is merged
+// (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
+// SC = start << 16 | count, in position order); a pool of one value is read
+// back from v.  When the pool on top is a single value, nothing merges until
+// the next violation v[j] > v[j+1] of the input (vio, increasing): the
+// values in between stay single pools and are skipped.  One thread builds the
+// pools, the block then writes their means.
+__host__ __device__ inline void pava_sparse(const double *v, int L, const int *vio, int nv, double *S, int *SC,
+                                   int *npools) {
 #pragma clang fp contract(off)
-    int nb = 0;
-    for (int i = 0; i < L; ++i) {
-        double s = v[i];
-        int c = 1;
-        while (nb > 0 && S[nb - 1] / (double)Cn[nb - 1] > s / (double)c) {
-            s += S[nb - 1];
-            c += Cn[nb - 1];
-            --nb;
+    int nb = 0, vi = 0;
+    int i = vio[0];
+    double tS = v[i], tM = tS;
+    int tC = 1, tSt = i;
+    ++i;
+    while (i < L) {
+        if (tC == 1) {
+            while (vi < nv && vio[vi] < i - 1) ++vi;
+            if (vi == nv) break;  // non-decreasing from v[i-1] on
+            const int jn = vio[vi];
+            if (jn > i - 1) {
+                tSt = jn;
+                tS = v[jn];
+                tM = tS;
+                i = jn + 1;
+            }
         }
-        S[nb] = s;
-        Cn[nb] = c;
+        double s = v[i], m = s;
+        int c = 1, st = i;
+        bool below = true;
+        while (below && tM > m) {
+            s = s + tS;
+            c = c + tC;
+            st = tSt;
+            if (tSt == 0) {
+                below = false;
+            } else if (nb > 0 && (SC[nb - 1] >> 16) + (SC[nb - 1] & 0xFFFF) == tSt) {
+                --nb;
+                tS = S[nb];
+                tC = SC[nb] & 0xFFFF;
+                tSt = SC[nb] >> 16;
+                tM = tS / (double)tC;
+            } else {
+                tSt = tSt - 1;
+                tS = v[tSt];
+                tC = 1;
+                tM = tS / 1.0;
+            }
+            m = s / (double)c;
+        }
+        if (below && tC > 1) {
+            S[nb] = tS;
+            SC[nb] = (tSt << 16) | tC;
+            ++nb;
+        }
+        tS = s;
+        tC = c;
+        tSt = st;
+        tM = m;
+        ++i;
+    }
+    if (tC > 1) {
+        S[nb] = tS;
+        SC[nb] = (tSt << 16) | tC;
         ++nb;
     }
-    int o = 0;
-    for (int b = 0; b < nb; ++b) {
-        const double m = S[b] / (double)Cn[b];
-        for (int t = 0; t < Cn[b]; ++t) v[o++] = m;
+    *npools = nb;
+}
+
+// Pool-adjacent-violators over v[0..L) (L < 65536) by the whole block, with
+// the arithmetic of the serial stack form: the violations v[j] > v[j+1] are found
+// in parallel; without any, v is already the result; otherwise one thread
+// builds the pools with pava_sparse and the block writes their means.  LDS:
+// S [L] doubles, SC and vio [L] ints.  Every thread of the block calls it.
+__device__ inline void pava_block(double *v, int L, double *S, int *SC, int *vio) {
+#pragma clang fp contract(off)
+    __shared__ int wsum[16], nbad, npools;
+    const int nt = (int)blockDim.x;
+    const int per = (L + nt - 1) / nt;
+    const int j0 = (int)threadIdx.x * per, j1 = min(j0 + per, L - 1);
+    int cnt = 0;
+    for (int j = j0; j < j1; ++j) cnt += v[j] > v[j + 1] ? 1 : 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
     }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int base = inc - cnt;
+    for (int k = 0; k < w; ++k) base += wsum[k];
+    for (int j = j0; j < j1; ++j)
+        if (v[j] > v[j + 1]) vio[base++] = j;
+    if ((int)threadIdx.x == nt - 1) nbad = base;
+    __syncthreads();
+    if (nbad == 0) return;
+    if (threadIdx.x == 0) pava_sparse(v, L, vio, nbad, S, SC, &npools);
+    __syncthreads();
+    for (int q = threadIdx.x; q < npools; q += nt) {
+        const int cq = SC[q] & 0xFFFF, st = SC[q] >> 16;
+        const double mean = S[q] / (double)cq;
+        for (int t = 0; t < cq; ++t) v[st + t] = mean;
+    }
+    __syncthreads();
 }
 
 }  // namespace pr

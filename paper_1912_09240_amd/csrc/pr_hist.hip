@@ -337,77 +337,6 @@ int hist_restrict(const double *x, const double *w, int64_t n, int64_t stride, i
 // Scratch of the quantile iterator per slice, in doubles.
 __host__ __device__ inline size_t jq_scratch_doubles(int cells) { return (size_t)6 * (cells + 1) + 8; }
 
-// Pool-adjacent-violators (equal weights) with the same additions, divisions
-// and comparisons as the textbook stack form: a new value starts a pool (sum
-// s, count c); while the pool below has a larger mean S/C it is merged
-// (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
-// SC = start << 16 | count, in position order); a pool of one value is read
-// back from v.  When the pool on top is a single value, nothing merges until
-// the next violation v[j] > v[j+1] of the input (vio, increasing): the
-// values in between stay single pools and are skipped.  One thread builds the
-// pools, the block then writes their means.
-__device__ inline void pava_sparse(const double *v, int L, const int *vio, int nv, double *S, int *SC,
-                                   int *npools) {
-#pragma clang fp contract(off)
-    int nb = 0, vi = 0;
-    int i = vio[0];
-    double tS = v[i], tM = tS;
-    int tC = 1, tSt = i;
-    ++i;
-    while (i < L) {
-        if (tC == 1) {
-            while (vi < nv && vio[vi] < i - 1) ++vi;
-            if (vi == nv) break;  // non-decreasing from v[i-1] on
-            const int jn = vio[vi];
-            if (jn > i - 1) {
-                tSt = jn;
-                tS = v[jn];
-                tM = tS;
-                i = jn + 1;
-            }
-        }
-        double s = v[i], m = s;
-        int c = 1, st = i;
-        bool below = true;
-        while (below && tM > m) {
-            s = s + tS;
-            c = c + tC;
-            st = tSt;
-            if (tSt == 0) {
-                below = false;
-            } else if (nb > 0 && (SC[nb - 1] >> 16) + (SC[nb - 1] & 0xFFFF) == tSt) {
-                --nb;
-                tS = S[nb];
-                tC = SC[nb] & 0xFFFF;
-                tSt = SC[nb] >> 16;
-                tM = tS / (double)tC;
-            } else {
-                tSt = tSt - 1;
-                tS = v[tSt];
-                tC = 1;
-                tM = tS / 1.0;
-            }
-            m = s / (double)c;
-        }
-        if (below && tC > 1) {
-            S[nb] = tS;
-            SC[nb] = (tSt << 16) | tC;
-            ++nb;
-        }
-        tS = s;
-        tC = c;
-        tSt = st;
-        tM = m;
-        ++i;
-    }
-    if (tC > 1) {
-        S[nb] = tS;
-        SC[nb] = (tSt << 16) | tC;
-        ++nb;
-    }
-    *npools = nb;
-}
-
 template <int KIND>
 __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict__ rc, const double *__restrict__ rf,
                                                         const double *__restrict__ rcs, int64_t in_stride,
@@ -688,12 +617,30 @@ struct HMatchArgs {
     const double *tab;         // match_tables output
 };
 
+// first index in [lo, hi) with a[i] >= v (hi if none)
+__device__ __forceinline__ int lower_bound_range(const double *a, int lo, int hi, double v) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Fast-marginal matching: X = q_t(cbar(Xbar)).  Grid (tiles, k).
+// The level cbar of a particle in prior cell i lies in [cp_i, cp_{i+1}], so
+// the first target edge whose cdf reaches it lies between s_i and s_{i+1},
+// s_i = the first target edge with cdf >= cp_i (a table in LDS): the search
+// covers the few target cells that overlap prior cell i.  When the level
+// falls strictly inside a target cell (no target edge has exactly this cdf
+// value) the quantile is that cell's linear interpolation, the same value as
+// the midpoint rule of the general case; otherwise the general rule runs.
 __global__ void __launch_bounds__(HB_THREADS) match_marginal_kernel(HMatchArgs a, HGrid g) {
 #pragma clang fp contract(off)
     extern __shared__ double sh[];
     const int s = blockIdx.y, I = g.cells;
     double *rp = sh, *rt = rp + I, *cp = rt + I, *ctg = cp + (I + 1);
+    int *st = (int *)(ctg + (I + 1));
     const double *tab = a.tab + (size_t)s * 3 * (I + 1);
     for (int i = threadIdx.x; i < I; i += blockDim.x) {
         rp[i] = a.rp[(int64_t)s * a.p_stride + i];
@@ -704,6 +651,9 @@ __global__ void __launch_bounds__(HB_THREADS) match_marginal_kernel(HMatchArgs a
         ctg[i] = tab[I + 1 + i];
     }
     __syncthreads();
+    for (int i = threadIdx.x; i <= I; i += blockDim.x) st[i] = lower_bound_range(ctg, 0, I + 1, cp[i]);
+    __syncthreads();
+    const double M = ctg[I];
     const double *x = a.x + (int64_t)s * a.x_stride;
     double *xo = a.xo + (int64_t)s * a.o_stride;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -711,7 +661,20 @@ __global__ void __launch_bounds__(HB_THREADS) match_marginal_kernel(HMatchArgs a
         const int i = hcell(g, xv);
         const double t = fmin(fmax((xv - hedge(g, i)) / g.h, 0.0), 1.0);
         const double cbar = cp[i] + t * rp[i];
-        xo[p] = quantile_hist(rt, ctg, g, cbar);
+        const double lv = fmin(fmax(cbar, 0.0), M);
+        double out;
+        if (lv >= cp[i] && lv <= cp[i + 1]) {
+            const int e = lower_bound_range(ctg, st[i], min(st[i + 1] + 1, I + 1), lv);
+            if (e >= 1 && e <= I && ctg[e] > lv) {
+                const double u = fmin(fmax((lv - ctg[e - 1]) / rt[e - 1], 0.0), 1.0);
+                out = hedge(g, e - 1) + u * g.h;
+            } else {
+                out = quantile_hist(rt, ctg, g, lv);
+            }
+        } else {
+            out = quantile_hist(rt, ctg, g, lv);
+        }
+        xo[p] = out;
     }
 }
 
@@ -897,7 +860,8 @@ int hist_match(int kind, const HMatchArgs &a0, int k, const HGrid &g, Key key, u
     const int per = (int)std::min<int64_t>(std::max<int64_t>((a.n + 4095) / 4096, 1), 256);
     const dim3 grid((unsigned)per, (unsigned)k);
     if (kind == PR_M_MARGINAL) {
-        hipLaunchKernelGGL(match_marginal_kernel, grid, dim3(HB_THREADS), sizeof(double) * (4 * g.cells + 2), st, a, g);
+        hipLaunchKernelGGL(match_marginal_kernel, grid, dim3(HB_THREADS),
+                           sizeof(double) * (4 * g.cells + 2) + sizeof(int) * (g.cells + 1), st, a, g);
         PR_LAUNCHED();
         return PR_OK;
     }
