@@ -186,6 +186,199 @@ __host__ __device__ inline void pava_sparse(const double *v, int L, const int *v
     *npools = nb;
 }
 
+// The sparse pass on the stretch [lo, hi) alone (vio: the violations inside
+// it, increasing; positions absolute): as if the stretch started the input.
+// Pools of more than one value go to S[lo + k], SC[lo + k].  Returns their
+// number; *fm receives the smallest of the means that the pool holding lo
+// takes (v[lo] first, then after every merge that reaches lo): the values the
+// serial pass over the whole input would compare with the mean of the last
+// pool before the stretch.  *lm receives the mean of the pool holding hi - 1.
+__host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi, const int *vio, int nv,
+                                                 double *S, int *SC, double *fm, double *lm) {
+#pragma clang fp contract(off)
+    int nb = 0, vi = 0;
+    double fmin_ = v[lo];
+    int i = vio[0];
+    double tS = v[i], tM = tS;
+    int tC = 1, tSt = i;
+    ++i;
+    while (i < hi) {
+        if (tC == 1) {
+            while (vi < nv && vio[vi] < i - 1) ++vi;
+            if (vi == nv) break;
+            const int jn = vio[vi];
+            if (jn > i - 1) {
+                tSt = jn;
+                tS = v[jn];
+                tM = tS;
+                i = jn + 1;
+            }
+        }
+        double s = v[i], m = s;
+        int c = 1, st = i;
+        bool below = true;
+        while (below && tM > m) {
+            s = s + tS;
+            c = c + tC;
+            st = tSt;
+            if (tSt == lo) {
+                below = false;
+            } else if (nb > 0 && (SC[lo + nb - 1] >> 16) + (SC[lo + nb - 1] & 0xFFFF) == tSt) {
+                --nb;
+                tS = S[lo + nb];
+                tC = SC[lo + nb] & 0xFFFF;
+                tSt = SC[lo + nb] >> 16;
+                tM = tS / (double)tC;
+            } else {
+                tSt = tSt - 1;
+                tS = v[tSt];
+                tC = 1;
+                tM = tS / 1.0;
+            }
+            m = s / (double)c;
+            if (st == lo && m < fmin_) fmin_ = m;
+        }
+        if (below && tC > 1) {
+            S[lo + nb] = tS;
+            SC[lo + nb] = (tSt << 16) | tC;
+            ++nb;
+        }
+        tS = s;
+        tC = c;
+        tSt = st;
+        tM = m;
+        ++i;
+    }
+    *lm = (i - 1 == hi - 1) ? tM : v[hi - 1];
+    if (tC > 1) {
+        S[lo + nb] = tS;
+        SC[lo + nb] = (tSt << 16) | tC;
+        ++nb;
+    }
+    *fm = fmin_;
+    return nb;
+}
+
+// Pool-adjacent-violators over v[0..L) by the whole block from its known
+// violations vio[0..nv) (increasing), with the arithmetic of the serial
+// stack form.  The violations are grouped into clusters (neighbours less
+// than three positions apart); the input is cut halfway between clusters and
+// every stretch runs pava_sparse_range on its own thread.  Where the last
+// pool of a stretch has a mean above a value the first pool of the next one
+// takes, the serial pass would have merged across the cut: those cuts are
+// dropped and the stretches run again, until no cut is crossed — then the
+// pools are those of the serial pass, sums and means bit for bit.  At most
+// PAVA_MAXC stretches (clusters beyond that are joined).  LDS: S [L]
+// doubles, SC [L] ints, and the stretch tables.
+constexpr int PAVA_MAXC = 512;
+
+struct PavaChunks {
+    int cb[PAVA_MAXC + 1];  // stretch bounds
+    int fv[PAVA_MAXC + 1];  // first violation of each stretch
+    int np[PAVA_MAXC];      // stored pools of each stretch
+    double fm[PAVA_MAXC], lm[PAVA_MAXC];
+    int nc, drop, wsum[16];
+};
+
+__device__ inline void pava_block_chunked(double *v, int L, const int *vio, int nv, double *S, int *SC,
+                                          PavaChunks &pc) {
+    const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    // cluster starts: violation f with vio[f] - vio[f-1] >= 3; keep at most
+    // PAVA_MAXC of them, evenly
+    {
+        const int per = (nv + nt - 1) / nt;
+        const int f0 = tid * per, f1 = min(f0 + per, nv);
+        int cnt = 0;
+        for (int f = f0; f < f1; ++f) cnt += (f == 0 || vio[f] - vio[f - 1] >= 3) ? 1 : 0;
+        int inc = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) pc.wsum[w] = inc;
+        __syncthreads();
+        int base = inc - cnt, total = 0;
+        for (int k = 0; k < nt / 64; ++k) {
+            if (k < w) base += pc.wsum[k];
+            total += pc.wsum[k];
+        }
+        const int stride = (total + PAVA_MAXC - 1) / PAVA_MAXC;
+        for (int f = f0; f < f1; ++f)
+            if (f == 0 || vio[f] - vio[f - 1] >= 3) {
+                if (base % stride == 0) {
+                    const int k = base / stride;
+                    pc.fv[k] = f;
+                    pc.cb[k] = f == 0 ? 0 : (vio[f - 1] + vio[f] + 2) >> 1;
+                }
+                ++base;
+            }
+        if (tid == 0) {
+            const int nc = (total + stride - 1) / stride;
+            pc.nc = nc;
+            pc.cb[nc] = L;
+            pc.fv[nc] = nv;
+        }
+        __syncthreads();
+    }
+    while (true) {
+        const int nc = pc.nc;
+        for (int k = tid; k < nc; k += nt)
+            pc.np[k] = pava_sparse_range(v, pc.cb[k], pc.cb[k + 1], vio + pc.fv[k], pc.fv[k + 1] - pc.fv[k], S, SC,
+                                         &pc.fm[k], &pc.lm[k]);
+        __syncthreads();
+        // keep cut k (1 <= k < nc) unless the serial pass would cross it
+        const int per = (nc + nt - 1) / nt;
+        const int k0 = tid * per, k1 = min(k0 + per, nc);
+        int cnt = 0;
+        for (int k = k0; k < k1; ++k) cnt += (k == 0 || !(pc.lm[k - 1] > pc.fm[k])) ? 1 : 0;
+        int inc = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) pc.wsum[w] = inc;
+        __syncthreads();
+        int base = inc - cnt, total = 0;
+        for (int k = 0; k < nt / 64; ++k) {
+            if (k < w) base += pc.wsum[k];
+            total += pc.wsum[k];
+        }
+        if (total == nc) break;  // every cut holds (uniform: total is the block's sum)
+        // compact the kept cuts in place: kept cut k moves to base <= k, so
+        // read every kept value before any write
+        int keep_cb[8], keep_fv[8], nk = 0;
+        for (int k = k0; k < k1 && nk < 8; ++k)
+            if (k == 0 || !(pc.lm[k - 1] > pc.fm[k])) {
+                keep_cb[nk] = pc.cb[k];
+                keep_fv[nk] = pc.fv[k];
+                ++nk;
+            }
+        __syncthreads();
+        for (int t = 0; t < nk; ++t) {
+            pc.cb[base + t] = keep_cb[t];
+            pc.fv[base + t] = keep_fv[t];
+        }
+        if (tid == 0) {
+            pc.nc = total;
+            pc.cb[total] = L;
+            pc.fv[total] = nv;
+        }
+        __syncthreads();
+    }
+    // write the means of the stored pools of every stretch
+    const int nc = pc.nc;
+    for (int k = tid; k < nc; k += nt) {
+        const int lo = pc.cb[k];
+        for (int b = 0; b < pc.np[k]; ++b) {
+            const int cq = SC[lo + b] & 0xFFFF, st = SC[lo + b] >> 16;
+            const double mean = S[lo + b] / (double)cq;
+            for (int t = 0; t < cq; ++t) v[st + t] = mean;
+        }
+    }
+    __syncthreads();
+}
+
 // Pool-adjacent-violators over v[0..L) (L < 65536) by the whole block, with
 // the arithmetic of the serial stack form: the violations v[j] > v[j+1] are found
 // in parallel; without any, v is already the result; otherwise one thread

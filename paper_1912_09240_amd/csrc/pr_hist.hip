@@ -40,6 +40,7 @@ constexpr int HB_THREADS = 256;
 constexpr int HB_ITEMS = 8;
 constexpr int HB_TILE = HB_THREADS * HB_ITEMS;  // particles per tile of the resampling
 constexpr int HB_MAX_CELLS = 1024;
+constexpr int JQ_THREADS = 1024;  // the quantile iterator: one workgroup per slice along a serial chain
 constexpr int FIX_W = 112;  // fraction bits of the histogram weights
 constexpr uint32_t TAG_RESAMPLE = 4u;
 
@@ -162,14 +163,14 @@ __device__ __forceinline__ int upper_bound_d(const double *a, int n, double v) {
     return lo;
 }
 
-// Quantile of the histogram rho (cdf c at the I + 1 edges) at level p.
-__device__ inline double quantile_hist(const double *rho, const double *c, const HGrid &g, double p) {
+// Quantile of the histogram rho (cdf c at the I + 1 edges) at a level p in
+// [0, M], given a = the first edge with c >= p and b = the last edge with
+// c <= p.
+__device__ inline double quantile_hist_ab(const double *rho, const double *c, const HGrid &g, double p, int a,
+                                          int b) {
 #pragma clang fp contract(off)
     const int I = g.cells;
     const double M = c[I];
-    p = fmin(fmax(p, 0.0), M);
-    const int a = lower_bound_d(c, I + 1, p);
-    const int b = upper_bound_d(c, I + 1, p) - 1;
     double L, R;
     if (a == 0) {
         L = hedge(g, 0);
@@ -187,6 +188,31 @@ __device__ inline double quantile_hist(const double *rho, const double *c, const
     if (p == M) return L;
     return 0.5 * (L + R);
 }
+
+// Quantile of the histogram rho (cdf c at the I + 1 edges) at level p.
+__device__ inline double quantile_hist(const double *rho, const double *c, const HGrid &g, double p) {
+    const int I = g.cells;
+    p = fmin(fmax(p, 0.0), c[I]);
+    return quantile_hist_ab(rho, c, g, p, lower_bound_d(c, I + 1, p), upper_bound_d(c, I + 1, p) - 1);
+}
+
+// Quantiles at non-decreasing levels by one thread: the edge indices of
+// quantile_hist found once by binary search, then advanced.
+struct QuantileWalk {
+    int a = -1, u = 0;  // first edge with c >= p, first edge with c > p
+    __device__ inline double at(const double *rho, const double *c, const HGrid &g, double p) {
+        const int E = g.cells + 1;
+        p = fmin(fmax(p, 0.0), c[E - 1]);
+        if (a < 0) {
+            a = lower_bound_d(c, E, p);
+            u = upper_bound_d(c, E, p);
+        } else {
+            while (a < E && c[a] < p) ++a;
+            while (u < E && c[u] <= p) ++u;
+        }
+        return quantile_hist_ab(rho, c, g, p, a, u - 1);
+    }
+};
 
 // Left-to-right running sums by one wave (lanes of wave 0 call it):
 // out[0] = 0, out[i+1] = out[i] + v(i) for i < n; returns the total to lane 0
@@ -338,7 +364,7 @@ int hist_restrict(const double *x, const double *w, int64_t n, int64_t stride, i
 __host__ __device__ inline size_t jq_scratch_doubles(int cells) { return (size_t)6 * (cells + 1) + 8; }
 
 template <int KIND>
-__global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict__ rc, const double *__restrict__ rf,
+__global__ void __launch_bounds__(KIND == PR_J_QUANTILE ? JQ_THREADS : HB_THREADS) hist_jump(const double *__restrict__ rc, const double *__restrict__ rf,
                                                         const double *__restrict__ rcs, int64_t in_stride,
                                                         double *__restrict__ out, int64_t out_stride, HGrid g,
                                                         double *__restrict__ scratch) {
@@ -402,40 +428,60 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
     } else {
         // quantile iterator on the union of the edge levels.  LDS: the three
         // edge cdfs (later the pool sums and the new edge cdf), the corrected
-        // quantiles, the pool counts; global scratch: merged and unique levels.
+        // quantiles (first the merged levels), the pool counts, the violations
+        // and the unique levels.
         extern __shared__ double jq[];
         const int E = I + 1, T3 = 3 * E;
         double *cc = jq, *cf = cc + E, *ccs = cf + E;  // [3E]
         double *qt = jq + T3;                           // [<= 3E]
         int *pC = (int *)(jq + 2 * T3);                 // [<= 3E]
-        double *sc = scratch + (size_t)s * jq_scratch_doubles(I);
-        double *merged = sc, *lev = sc + T3;            // [3E] each
+        double *merged = qt;                            // [3E], dead once the levels are unique
+        double *lev = (double *)(pC + 2 * T3);          // [3E]
+        (void)scratch;
         __shared__ int nU, bad;
         const int wave = threadIdx.x >> 6;
         if (wave == 0) wave_running_sum([&](int i) { return rc[i]; }, I, cc);
         if (wave == 1) wave_running_sum([&](int i) { return rf[i]; }, I, cf);
         if (wave == 2) wave_running_sum([&](int i) { return rcs[i]; }, I, ccs);
         __syncthreads();
-        // stable merge by rank: (value, array, index)
-        for (int e = threadIdx.x; e < T3; e += blockDim.x) {
-            const int arr = e / E, idx = e % E;
-            const double *A = arr == 0 ? cc : arr == 1 ? cf : ccs;
-            const double v = A[idx];
-            int pos = idx;
-            if (arr == 0) pos += lower_bound_d(cf, E, v) + lower_bound_d(ccs, E, v);
-            else if (arr == 1) pos += upper_bound_d(cc, E, v) + lower_bound_d(ccs, E, v);
-            else pos += upper_bound_d(cc, E, v) + upper_bound_d(cf, E, v);
-            merged[pos] = v;
+        // stable merge by rank: (value, array, index).  Every thread takes a
+        // contiguous run of one array's (non-decreasing) values; the ranks in
+        // the other two arrays come from one binary search each, then advance.
+        {
+            const int per = (T3 + JQ_THREADS - 1) / JQ_THREADS;
+            const int e0 = threadIdx.x * per, e1 = min(e0 + per, T3);
+            int cur = -1, r1 = 0, r2 = 0;
+            for (int e = e0; e < e1; ++e) {
+                const int arr = e / E, idx = e % E;
+                const double *A = arr == 0 ? cc : arr == 1 ? cf : ccs;
+                const double *B1 = arr == 0 ? cf : cc;   // first other array
+                const double *B2 = arr == 2 ? cf : ccs;  // second other array
+                const double v = A[idx];
+                // ties: an earlier array's equal values come first
+                const bool strict1 = arr == 0;  // B1 later than A: count B1 < v; else B1 <= v
+                const bool strict2 = arr != 2;  // B2 later than A: count B2 < v; else B2 <= v
+                if (arr != cur) {
+                    cur = arr;
+                    r1 = strict1 ? lower_bound_d(B1, E, v) : upper_bound_d(B1, E, v);
+                    r2 = strict2 ? lower_bound_d(B2, E, v) : upper_bound_d(B2, E, v);
+                } else {
+                    if (strict1) while (r1 < E && B1[r1] < v) ++r1;
+                    else while (r1 < E && B1[r1] <= v) ++r1;
+                    if (strict2) while (r2 < E && B2[r2] < v) ++r2;
+                    else while (r2 < E && B2[r2] <= v) ++r2;
+                }
+                merged[idx + r1 + r2] = v;
+            }
         }
         __syncthreads();
         // unique levels: compaction of the first of every run of equal values,
         // every thread owning a contiguous chunk of the merged levels
         {
-            const int per = (T3 + HB_THREADS - 1) / HB_THREADS;
+            const int per = (T3 + JQ_THREADS - 1) / JQ_THREADS;
             const int i0 = threadIdx.x * per, i1 = min(i0 + per, T3);
             int cnt = 0;
             for (int i = i0; i < i1; ++i) cnt += (i == 0 || merged[i] != merged[i - 1]) ? 1 : 0;
-            __shared__ int wsum[HB_THREADS / 64];
+            __shared__ int wsum[JQ_THREADS / 64];
             const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
             int inc = cnt;
             for (int off = 1; off < 64; off <<= 1) {
@@ -448,24 +494,31 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
             for (int k2 = 0; k2 < w; ++k2) base += wsum[k2];
             for (int i = i0; i < i1; ++i)
                 if (i == 0 || merged[i] != merged[i - 1]) lev[base++] = merged[i];
-            if (threadIdx.x == HB_THREADS - 1) nU = base;
+            if (threadIdx.x == JQ_THREADS - 1) nU = base;
         }
         __syncthreads();
         const int U = nU;
-        for (int j = threadIdx.x; j < U; j += blockDim.x) {
-            const double p = lev[j];
-            qt[j] = quantile_hist(rf, cf, g, p) + (quantile_hist(rc, cc, g, p) - quantile_hist(rcs, ccs, g, p));
+        {  // every thread a contiguous run of the (increasing) levels
+            const int per = (U + JQ_THREADS - 1) / JQ_THREADS;
+            const int j0 = threadIdx.x * per, j1 = min(j0 + per, U);
+            QuantileWalk wf, wc, wcs;
+            for (int j = j0; j < j1; ++j) {
+                const double p = lev[j];
+                const double qf = wf.at(rf, cf, g, p);
+                const double qc = wc.at(rc, cc, g, p);
+                const double qcs = wcs.at(rcs, ccs, g, p);
+                qt[j] = qf + (qc - qcs);
+            }
         }
         __syncthreads();
-        // violations qt[j] > qt[j+1], in increasing j, compacted into vio (the
-        // upper half of the cdfs' LDS; the pools' sums use the lower half)
-        int *vio = (int *)(jq + (T3 + 1) / 2);
+        // violations qt[j] > qt[j+1], in increasing j, compacted into vio
+        int *vio = pC + T3;
         {
-            const int per = (U + HB_THREADS - 1) / HB_THREADS;
+            const int per = (U + JQ_THREADS - 1) / JQ_THREADS;
             const int j0 = threadIdx.x * per, j1 = min(j0 + per, U - 1);
             int cnt = 0;
             for (int j = j0; j < j1; ++j) cnt += qt[j] > qt[j + 1] ? 1 : 0;
-            __shared__ int vsum[HB_THREADS / 64];
+            __shared__ int vsum[JQ_THREADS / 64];
             const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
             int inc = cnt;
             for (int off = 1; off < 64; off <<= 1) {
@@ -478,23 +531,20 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
             for (int k2 = 0; k2 < w; ++k2) base += vsum[k2];
             for (int j = j0; j < j1; ++j)
                 if (qt[j] > qt[j + 1]) vio[base++] = j;
-            if (threadIdx.x == HB_THREADS - 1) bad = base;
+            if (threadIdx.x == JQ_THREADS - 1) bad = base;
         }
         __syncthreads();
-        if (bad > 0) {  // the cdfs are no longer needed: their LDS holds the pools
-            __shared__ int npools;
-            if (threadIdx.x == 0) pava_sparse(qt, U, vio, bad, jq, pC, &npools);
-            __syncthreads();
-            for (int b = threadIdx.x; b < npools; b += blockDim.x) {
-                const int c = pC[b] & 0xFFFF, st = pC[b] >> 16;
-                const double mean = jq[b] / (double)c;
-                for (int t = 0; t < c; ++t) qt[st + t] = mean;
-            }
+        if (bad > 0) {  // the cdfs are no longer needed: their LDS holds the pools' sums
+            __shared__ PavaChunks pcs;
+            pava_block_chunked(qt, U, vio, bad, jq, pC, pcs);
         }
         __syncthreads();
         // cdf at the edges: inf{p : q(p) >= x_i} on the piecewise-linear q
         double *ct = jq;  // [E], over the pool sums
-        for (int i = threadIdx.x; i < E; i += blockDim.x) {
+        const int iper = (E + JQ_THREADS - 1) / JQ_THREADS;
+        const int i0 = threadIdx.x * iper, i1 = min(i0 + iper, E);
+        int jw = -1;  // first level with qt >= x, advanced along the thread's edges
+        for (int i = i0; i < i1; ++i) {
             double v;
             if (i == 0) {
                 v = 0.0;
@@ -502,7 +552,9 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
                 v = lev[U - 1];
             } else {
                 const double x = hedge(g, i);
-                const int j = lower_bound_d(qt, U, x);
+                if (jw < 0) jw = lower_bound_d(qt, U, x);
+                else while (jw < U && qt[jw] < x) ++jw;
+                const int j = jw;
                 if (j == 0) v = 0.0;
                 else if (j == U) v = lev[U - 1];
                 else {
@@ -517,7 +569,7 @@ __global__ void __launch_bounds__(HB_THREADS) hist_jump(const double *__restrict
     }
 }
 
-static size_t jq_lds_bytes(int cells) { return (sizeof(double) * 2 + sizeof(int)) * 3 * (size_t)(cells + 1); }
+static size_t jq_lds_bytes(int cells) { return (sizeof(double) * 3 + sizeof(int) * 2) * 3 * (size_t)(cells + 1); }
 
 size_t hist_jump_ws_bytes(int k, int cells) { return sizeof(double) * jq_scratch_doubles(cells) * (size_t)k + 256; }
 
@@ -538,7 +590,7 @@ int hist_jump_launch(int kind, const double *rc, const double *rf, const double 
                                out_stride, g, scratch);
             break;
         default:
-            hipLaunchKernelGGL(hist_jump<PR_J_QUANTILE>, dim3(k), dim3(HB_THREADS), jq_lds_bytes(g.cells), st, rc, rf,
+            hipLaunchKernelGGL(hist_jump<PR_J_QUANTILE>, dim3(k), dim3(JQ_THREADS), jq_lds_bytes(g.cells), st, rc, rf,
                                rcs, in_stride, out, out_stride, g, scratch);
     }
     PR_LAUNCHED();

@@ -22,3 +22,55 @@ extern "C" int pv_pava_sparse(double *v, int L) {
     }
     return np;
 }
+
+// The stretch decomposition of the block pass, run serially: violations
+// grouped into clusters (neighbours less than three apart), stretches cut
+// halfway between clusters, each stretch by pava_sparse_range, cuts that the
+// serial pass would cross dropped until none is.  Returns the rounds.
+extern "C" int pv_pava_stretches(double *v, int L) {
+    std::vector<int> vio;
+    for (int j = 0; j + 1 < L; ++j)
+        if (v[j] > v[j + 1]) vio.push_back(j);
+    const int nv = (int)vio.size();
+    if (nv == 0) return 0;
+    std::vector<int> cb, fv;
+    for (int f = 0; f < nv; ++f)
+        if (f == 0 || vio[f] - vio[f - 1] >= 3) {
+            fv.push_back(f);
+            cb.push_back(f == 0 ? 0 : (vio[f - 1] + vio[f] + 2) >> 1);
+        }
+    cb.push_back(L);
+    fv.push_back(nv);
+    std::vector<double> S(L), fm, lm;
+    std::vector<int> SC(L), np;
+    int rounds = 0;
+    while (true) {
+        ++rounds;
+        const int nc = (int)cb.size() - 1;
+        fm.assign(nc, 0.0);
+        lm.assign(nc, 0.0);
+        np.assign(nc, 0);
+        for (int k = 0; k < nc; ++k)
+            np[k] = pr::pava_sparse_range(v, cb[k], cb[k + 1], vio.data() + fv[k], fv[k + 1] - fv[k], S.data(),
+                                          SC.data(), &fm[k], &lm[k]);
+        std::vector<int> ncb{cb[0]}, nfv{fv[0]};
+        for (int k = 1; k < nc; ++k)
+            if (!(lm[k - 1] > fm[k])) {
+                ncb.push_back(cb[k]);
+                nfv.push_back(fv[k]);
+            }
+        if ((int)ncb.size() == nc) break;
+        ncb.push_back(L);
+        nfv.push_back(nv);
+        cb.swap(ncb);
+        fv.swap(nfv);
+    }
+    const int nc = (int)cb.size() - 1;
+    for (int k = 0; k < nc; ++k)
+        for (int b = 0; b < np[k]; ++b) {
+            const int c = SC[cb[k] + b] & 0xFFFF, st = SC[cb[k] + b] >> 16;
+            const double mean = S[cb[k] + b] / (double)c;
+            for (int t = 0; t < c; ++t) v[st + t] = mean;
+        }
+    return rounds;
+}

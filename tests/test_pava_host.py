@@ -29,6 +29,8 @@ def pv():
     L = ctypes.CDLL(so)
     L.pv_pava_sparse.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.pv_pava_sparse.restype = ctypes.c_int
+    L.pv_pava_stretches.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.pv_pava_stretches.restype = ctypes.c_int
     return L
 
 
@@ -45,12 +47,47 @@ def _cases():
     yield x
     yield np.array([1.0, 1.0, 0.0, 2.0, 1.5, 1.5, 1.5, 0.5, 4.0])
     yield np.array([3.0])
+    # zig-zag runs: violations every other position, as where the levels of
+    # three cdfs interleave
+    z = np.cumsum(rng.random(2000) * 1e-3)
+    z[1::2] -= 2e-3 * rng.random(1000)
+    yield z
+    w = np.cumsum(rng.random(3000))
+    for c0 in (200, 900, 1500, 2600):
+        w[c0:c0 + 60:2] += 3.0
+    yield w
 
 
-@pytest.mark.parametrize("case", list(range(9)))
+@pytest.mark.parametrize("case", list(range(11)))
 def test_sparse_pava_is_the_stack_form_bitwise(pv, case):
     v = list(_cases())[case].astype(np.float64)
     ref = OI.pava(v.copy())
     got = np.ascontiguousarray(v.copy())
     pv.pv_pava_sparse(got.ctypes.data_as(ctypes.c_void_p), len(got))
     assert np.array_equal(got, np.asarray(ref)), np.abs(got - ref).max()
+
+
+@pytest.mark.parametrize("case", list(range(11)))
+def test_stretch_decomposition_is_the_stack_form_bitwise(pv, case):
+    """The stretches of the block pass, each on its own, with the cuts that
+    the serial pass would cross dropped: the stack form's result bit for bit."""
+    v = list(_cases())[case].astype(np.float64)
+    ref = np.asarray(OI.pava(v.copy()))
+    got = np.ascontiguousarray(v.copy())
+    pv.pv_pava_stretches(got.ctypes.data_as(ctypes.c_void_p), len(got))
+    assert np.array_equal(got, ref), np.abs(got - ref).max()
+
+
+def test_stretch_decomposition_on_random_walks(pv):
+    rng = np.random.default_rng(5)
+    rounds = []
+    for t in range(300):
+        n = int(rng.integers(2, 400))
+        v = np.cumsum(rng.normal(rng.random() * 0.1, 1.0, n))
+        if t % 3 == 0:
+            v = np.round(v)  # ties
+        ref = np.asarray(OI.pava(v.copy()))
+        got = np.ascontiguousarray(v.copy())
+        rounds.append(pv.pv_pava_stretches(got.ctypes.data_as(ctypes.c_void_p), n))
+        assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
+    assert max(rounds) > 1  # cuts that had to be dropped were exercised
