@@ -104,15 +104,32 @@ __host__ __device__ inline uint64_t fix_weight(double w) {
 // U_j = floor(j T / P) + floor(k_j T / (P 2^32)), with T = qT P + rT:
 //   floor(j T / P)          = j qT + floor(j rT / P)
 //   floor(k T / (P 2^32))   = (k qT + floor(k rT / P)) >> 32
-// (j rT and k rT stay below 2^64, so two 64-bit divisions suffice).
+// (j rT and k rT stay below 2^64 with quotients below 2^32).
 struct SlotConst {
     u128 qT;
     uint64_t rT;
+    double inv_p;  // 1/P, rounded
 };
 
+// floor(a / P) for a < 2^64 whose quotient is below 2^32: the double
+// estimate a (1/P) is within a few units, the remainder fixes it exactly.
+__host__ __device__ inline uint64_t floor_div_p(uint64_t a, uint32_t P, double inv_p) {
+    uint64_t q = (uint64_t)((double)a * inv_p);
+    int64_t r = (int64_t)(a - q * (uint64_t)P);
+    while (r < 0) {
+        --q;
+        r += (int64_t)P;
+    }
+    while (r >= (int64_t)P) {
+        ++q;
+        r -= (int64_t)P;
+    }
+    return q;
+}
+
 __host__ __device__ inline u128 slot_level(uint64_t j, uint32_t kj, const SlotConst &c, uint32_t P) {
-    const u128 a = (u128)j * c.qT + (u128)((j * c.rT) / P);
-    const u128 b = ((u128)kj * c.qT + (u128)(((uint64_t)kj * c.rT) / P)) >> 32;
+    const u128 a = (u128)j * c.qT + (u128)floor_div_p(j * c.rT, P, c.inv_p);
+    const u128 b = ((u128)kj * c.qT + (u128)floor_div_p((uint64_t)kj * c.rT, P, c.inv_p)) >> 32;
     return a + b;
 }
 
@@ -679,6 +696,8 @@ __device__ __forceinline__ int lower_bound_range(const double *a, int lo, int hi
     return lo;
 }
 
+constexpr int MM_THREADS = 512;
+
 // Fast-marginal matching: X = q_t(cbar(Xbar)).  Grid (tiles, k).
 // The level cbar of a particle in prior cell i lies in [cp_i, cp_{i+1}], so
 // the first target edge whose cdf reaches it lies between s_i and s_{i+1},
@@ -687,7 +706,7 @@ __device__ __forceinline__ int lower_bound_range(const double *a, int lo, int hi
 // falls strictly inside a target cell (no target edge has exactly this cdf
 // value) the quantile is that cell's linear interpolation, the same value as
 // the midpoint rule of the general case; otherwise the general rule runs.
-__global__ void __launch_bounds__(HB_THREADS) match_marginal_kernel(HMatchArgs a, HGrid g) {
+__global__ void __launch_bounds__(MM_THREADS) match_marginal_kernel(HMatchArgs a, HGrid g) {
 #pragma clang fp contract(off)
     extern __shared__ double sh[];
     const int s = blockIdx.y, I = g.cells;
@@ -744,7 +763,7 @@ __global__ void __launch_bounds__(HB_THREADS) reweight_kernel(HMatchArgs a, HGri
 // Inclusive prefix of one u128 per thread over the block, in thread order;
 // *total receives the block's sum.
 __device__ inline u128 block_inclusive_u128(u128 v, u128 *total) {
-    __shared__ uint64_t wt[HB_THREADS / 64][2];
+    __shared__ uint64_t wt[16][2];  // blocks of up to 1024 threads
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     u128 inc = v;
     for (int off = 1; off < 64; off <<= 1) {
@@ -758,7 +777,7 @@ __device__ inline u128 block_inclusive_u128(u128 v, u128 *total) {
     }
     __syncthreads();
     u128 pre = 0, tot = 0;
-    for (int k2 = 0; k2 < HB_THREADS / 64; ++k2) {
+    for (int k2 = 0; k2 < (int)(blockDim.x >> 6); ++k2) {
         const u128 t = (u128)wt[k2][0] | ((u128)wt[k2][1] << 64);
         if (k2 < w) pre += t;
         tot += t;
@@ -802,23 +821,32 @@ __global__ void __launch_bounds__(HB_THREADS) resample_tile_sums(HMatchArgs a, H
 }
 
 // Pass 2: exclusive prefix over the tiles of every slice, and the total.
-__global__ void resample_tile_scan(uint64_t *__restrict__ tsum, int ntile, int64_t P, uint64_t *__restrict__ total) {
+// One block per slice, HB_THREADS tiles at a time.
+__global__ void __launch_bounds__(HB_THREADS) resample_tile_scan(uint64_t *__restrict__ tsum, int ntile, int64_t P,
+                                                                 uint64_t *__restrict__ total) {
     const int s = blockIdx.x;
-    if (threadIdx.x != 0) return;
     uint64_t *t = tsum + 2 * (int64_t)s * ntile;
     u128 run = 0;
-    for (int i = 0; i < ntile; ++i) {
-        const u128 v = (u128)t[2 * i] | ((u128)t[2 * i + 1] << 64);
-        t[2 * i] = (uint64_t)run;
-        t[2 * i + 1] = (uint64_t)(run >> 64);
-        run += v;
+    for (int c0 = 0; c0 < ntile; c0 += HB_THREADS) {
+        const int i = c0 + (int)threadIdx.x;
+        const u128 v = i < ntile ? ((u128)t[2 * i] | ((u128)t[2 * i + 1] << 64)) : (u128)0;
+        u128 chunk;
+        const u128 inc = block_inclusive_u128(v, &chunk);
+        if (i < ntile) {
+            const u128 ex = run + (inc - v);
+            t[2 * i] = (uint64_t)ex;
+            t[2 * i + 1] = (uint64_t)(ex >> 64);
+        }
+        run += chunk;
     }
-    total[5 * s] = (uint64_t)run;
-    total[5 * s + 1] = (uint64_t)(run >> 64);
-    const u128 qT = udiv128_32(run, (uint32_t)P);
-    total[5 * s + 2] = (uint64_t)qT;
-    total[5 * s + 3] = (uint64_t)(qT >> 64);
-    total[5 * s + 4] = (uint64_t)(run - qT * (u128)P);
+    if (threadIdx.x == 0) {
+        total[5 * s] = (uint64_t)run;
+        total[5 * s + 1] = (uint64_t)(run >> 64);
+        const u128 qT = udiv128_32(run, (uint32_t)P);
+        total[5 * s + 2] = (uint64_t)qT;
+        total[5 * s + 3] = (uint64_t)(qT >> 64);
+        total[5 * s + 4] = (uint64_t)(run - qT * (u128)P);
+    }
 }
 
 // first slot j in [0, P] with U_j >= C (U is non-decreasing in j), from the
@@ -833,17 +861,20 @@ __device__ inline int64_t first_slot_at(u128 C, u128 T, double Td, const SlotCon
     return j;
 }
 
+constexpr int RS_THREADS = 512, RS_ITEMS = HB_TILE / RS_THREADS;
+
 // Pass 3: the slots of a tile.  The block lays the cumulative weights of its
 // particles out in LDS, finds the slots j whose level U_j falls inside the
 // tile's weight range, and gives each of them the particle p with
 // C_p <= U_j < C_{p+1} (the first whose inclusive sum exceeds U_j).
-__global__ void __launch_bounds__(HB_THREADS) resample_slots_kernel(HMatchArgs a, HGrid g, double w0, int ntile,
+__global__ void __launch_bounds__(RS_THREADS) resample_slots_kernel(HMatchArgs a, HGrid g, double w0, int ntile,
                                                                     const uint64_t *__restrict__ tsum,
                                                                     const uint64_t *__restrict__ total, Key key,
                                                                     uint32_t inst, int t_first, int det) {
     __shared__ double r[HB_MAX_CELLS];
     __shared__ uint64_t cum[HB_TILE][2];  // inclusive cumulative weight of every particle of the tile
     __shared__ int64_t jr[2];
+    __shared__ int sidx[HB_TILE];  // particle of every slot of a batch
     const int s = blockIdx.y;
     load_ratio(a, g, s, r);
     const double *x = a.x + (int64_t)s * a.x_stride;
@@ -857,40 +888,68 @@ __global__ void __launch_bounds__(HB_THREADS) resample_slots_kernel(HMatchArgs a
     SlotConst sc;
     sc.qT = (u128)total[5 * s + 2] | ((u128)total[5 * s + 3] << 64);
     sc.rT = total[5 * s + 4];
+    sc.inv_p = 1.0 / (double)P;
     const double Td = fix_to_double(T, 0);
     const uint64_t *tp = tsum + 2 * ((int64_t)s * ntile + blockIdx.x);
     const u128 start = (u128)tp[0] | ((u128)tp[1] << 64);
     const uint32_t tpnt = (uint32_t)(t_first + s);
     const int64_t t0 = (int64_t)blockIdx.x * HB_TILE;
     const int np = (int)((a.n - t0) < HB_TILE ? (a.n - t0) : HB_TILE);
-    u128 row0 = start;
-    for (int i = 0; i < HB_ITEMS; ++i) {
-        const int idx = i * HB_THREADS + threadIdx.x;
+    // every thread sums RS_ITEMS consecutive particles, one block scan of
+    // the thread sums places them (integer sums: the order is immaterial)
+    u128 c = 0, own[RS_ITEMS];
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int idx = (int)threadIdx.x * RS_ITEMS + i;
         const int64_t p = t0 + idx;
-        const uint64_t q = idx < np ? fix_weight((w ? w[p] : w0) * r[hcell(g, x[p])]) : 0ull;
-        u128 rowtot;
-        const u128 c = row0 + block_inclusive_u128((u128)q, &rowtot);
-        cum[idx][0] = (uint64_t)c;
-        cum[idx][1] = (uint64_t)(c >> 64);
-        row0 += rowtot;
+        c += (u128)(idx < np ? fix_weight((w ? w[p] : w0) * r[hcell(g, x[p])]) : 0ull);
+        own[i] = c;
     }
+    u128 tile_total;
+    const u128 before = start + (block_inclusive_u128(c, &tile_total) - c);
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int idx = (int)threadIdx.x * RS_ITEMS + i;
+        const u128 v = before + own[i];
+        cum[idx][0] = (uint64_t)v;
+        cum[idx][1] = (uint64_t)(v >> 64);
+    }
+    const u128 row0 = start + tile_total;
     if (threadIdx.x == 0) jr[0] = first_slot_at(start, T, Td, sc, P, key, inst, tpnt, det);
     if (threadIdx.x == 64)
         jr[1] = (int)blockIdx.x == ntile - 1 ? (int64_t)P : first_slot_at(row0, T, Td, sc, P, key, inst, tpnt, det);
     __syncthreads();
-    for (int64_t j = jr[0] + threadIdx.x; j < jr[1]; j += HB_THREADS) {
-        const u128 U = slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), sc, P);
-        int lo = 0, hi = np - 1;  // first idx with cum[idx] > U (the last particle takes the rest)
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            const u128 cm = (u128)cum[mid][0] | ((u128)cum[mid][1] << 64);
-            if (cm > U) hi = mid;
-            else lo = mid + 1;
+    // slots in batches of HB_TILE: every thread finds the particles of a
+    // contiguous run of slots (one binary search, then a walk: U_j grows
+    // with j), then the block copies them with coalesced stores
+    for (int64_t jb = jr[0]; jb < jr[1]; jb += HB_TILE) {
+        const int nb = (int)((jr[1] - jb) < HB_TILE ? (jr[1] - jb) : HB_TILE);
+        const int per = (nb + RS_THREADS - 1) / RS_THREADS;
+        const int s0 = (int)threadIdx.x * per, s1 = min(s0 + per, nb);
+        int idx = -1;  // first idx with cum[idx] > U (the last particle takes the rest)
+        for (int t = s0; t < s1; ++t) {
+            const int64_t j = jb + t;
+            const u128 U = slot_level((uint64_t)j, slot_draw(key, inst, (uint32_t)j, tpnt, det), sc, P);
+            if (idx < 0) {
+                int lo = 0, hi = np - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const u128 cm = (u128)cum[mid][0] | ((u128)cum[mid][1] << 64);
+                    if (cm > U) hi = mid;
+                    else lo = mid + 1;
+                }
+                idx = lo;
+            } else {
+                while (idx < np - 1 && !(((u128)cum[idx][0] | ((u128)cum[idx][1] << 64)) > U)) ++idx;
+            }
+            sidx[t] = idx;
         }
-        const int64_t p = t0 + lo;
-        xo[j] = x[p];
-        for (int c = 0; c < a.d; ++c) yo[(int64_t)c * a.n + j] = y[(int64_t)c * a.n + p];
-        wo[j] = w0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb; t += RS_THREADS) {
+            const int64_t j = jb + t, p = t0 + sidx[t];
+            xo[j] = x[p];
+            for (int c = 0; c < a.d; ++c) yo[(int64_t)c * a.n + j] = y[(int64_t)c * a.n + p];
+            wo[j] = w0;
+        }
+        __syncthreads();
     }
 }
 
@@ -912,7 +971,7 @@ int hist_match(int kind, const HMatchArgs &a0, int k, const HGrid &g, Key key, u
     const int per = (int)std::min<int64_t>(std::max<int64_t>((a.n + 4095) / 4096, 1), 256);
     const dim3 grid((unsigned)per, (unsigned)k);
     if (kind == PR_M_MARGINAL) {
-        hipLaunchKernelGGL(match_marginal_kernel, grid, dim3(HB_THREADS),
+        hipLaunchKernelGGL(match_marginal_kernel, grid, dim3(MM_THREADS),
                            sizeof(double) * (4 * g.cells + 2) + sizeof(int) * (g.cells + 1), st, a, g);
         PR_LAUNCHED();
         return PR_OK;
@@ -928,9 +987,9 @@ int hist_match(int kind, const HMatchArgs &a0, int k, const HGrid &g, Key key, u
     const dim3 tgrid((unsigned)ntile, (unsigned)k);
     hipLaunchKernelGGL(resample_tile_sums, tgrid, dim3(HB_THREADS), 0, st, a, g, w0, ntile, tsum);
     PR_LAUNCHED();
-    hipLaunchKernelGGL(resample_tile_scan, dim3(k), dim3(64), 0, st, tsum, ntile, a.n, total);
+    hipLaunchKernelGGL(resample_tile_scan, dim3(k), dim3(HB_THREADS), 0, st, tsum, ntile, a.n, total);
     PR_LAUNCHED();
-    hipLaunchKernelGGL(resample_slots_kernel, tgrid, dim3(HB_THREADS), 0, st, a, g, w0, ntile, (const uint64_t *)tsum,
+    hipLaunchKernelGGL(resample_slots_kernel, tgrid, dim3(RS_THREADS), 0, st, a, g, w0, ntile, (const uint64_t *)tsum,
                        (const uint64_t *)total, key, inst, t_first, kind == PR_M_RESAMPLE_DET ? 1 : 0);
     PR_LAUNCHED();
     return PR_OK;
