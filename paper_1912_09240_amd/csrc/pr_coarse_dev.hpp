@@ -261,15 +261,17 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
 
 // Pool-adjacent-violators over v[0..L) by the whole block from its known
 // violations vio[0..nv) (increasing), with the arithmetic of the serial
-// stack form.  The violations are grouped into clusters (neighbours less
-// than three positions apart); the input is cut halfway between clusters and
-// every stretch runs pava_sparse_range on its own thread.  Where the last
-// pool of a stretch has a mean above a value the first pool of the next one
-// takes, the serial pass would have merged across the cut: those cuts are
-// dropped and the stretches run again, until no cut is crossed — then the
-// pools are those of the serial pass, sums and means bit for bit.  At most
-// PAVA_MAXC stretches (clusters beyond that are joined).  LDS: S [L]
-// doubles, SC [L] ints, and the stretch tables.
+// stack form.  The input is cut where every value before is below every
+// value after (no pool can reach across such a cut); the stretches between
+// cuts that hold violations run pava_sparse_range, one thread each.  Where
+// the last pool of a stretch has a mean above a value the first pool of the
+// next one takes (rounding can put a pool's mean above its largest value),
+// the serial pass would have merged across the cut: those cuts are dropped
+// and the stretches run again, until no cut is crossed -- then the pools are
+// those of the serial pass, sums and means bit for bit.  At most PAVA_MAXC
+// stretches (neighbours beyond that are joined).  LDS: S [L] doubles, SC [L]
+// ints (first the last cut at or before every position), and the stretch
+// tables.
 constexpr int PAVA_MAXC = 512;
 
 struct PavaChunks {
@@ -277,6 +279,7 @@ struct PavaChunks {
     int fv[PAVA_MAXC + 1];  // first violation of each stretch
     int np[PAVA_MAXC];      // stored pools of each stretch
     double fm[PAVA_MAXC], lm[PAVA_MAXC];
+    double wmax[16], wmin[16];
     int nc, drop, wsum[16];
 };
 
@@ -284,13 +287,68 @@ __device__ inline void pava_block_chunked(double *v, int L, const int *vio, int 
                                           PavaChunks &pc) {
     const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    // cluster starts: violation f with vio[f] - vio[f-1] >= 3; keep at most
-    // PAVA_MAXC of them, evenly
+    // Cuts: positions b with max(v[0..b)) < min(v[b..L)), where no pool can
+    // reach across.  Every thread takes a contiguous run of the values.
+    const int per = (L + nt - 1) / nt;
+    const int j0 = min(tid * per, L), j1 = min(j0 + per, L);
     {
-        const int per = (nv + nt - 1) / nt;
-        const int f0 = tid * per, f1 = min(f0 + per, nv);
+        double cmax = -INFINITY, cmin = INFINITY;
+        for (int j = j0; j < j1; ++j) {
+            cmax = fmax(cmax, v[j]);
+            cmin = fmin(cmin, v[j]);
+        }
+        // exclusive prefix max and exclusive suffix min over the threads' runs
+        double pmx = cmax, smn = cmin;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double u = __shfl_up(pmx, off), d = __shfl_down(smn, off);
+            if (lane >= off) pmx = fmax(pmx, u);
+            if (lane + off < 64) smn = fmin(smn, d);
+        }
+        if (lane == 63) pc.wmax[w] = pmx;
+        if (lane == 0) pc.wmin[w] = smn;
+        __syncthreads();
+        double before = __shfl_up(pmx, 1), after = __shfl_down(smn, 1);
+        if (lane == 0) before = -INFINITY;
+        if (lane == 63) after = INFINITY;
+        for (int k = 0; k < nt / 64; ++k) {
+            if (k < w) before = fmax(before, pc.wmax[k]);
+            if (k > w) after = fmin(after, pc.wmin[k]);
+        }
+        // cut flags of the run: SC[b] = b at a cut, else 0
+        double run_max = before;
+        for (int b = j0; b < j1; ++b) {
+            double suf = after;
+            for (int j = j1 - 1; j >= b; --j) suf = fmin(suf, v[j]);
+            SC[b] = (b > 0 && run_max < suf) ? b : 0;
+            run_max = fmax(run_max, v[b]);
+        }
+        __syncthreads();
+        // SC[j] = the last cut at or before j: inclusive prefix max
+        int rmx = 0;
+        for (int j = j0; j < j1; ++j) rmx = max(rmx, SC[j]);
+        int inc = rmx;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(inc, off);
+            if (lane >= off) inc = max(inc, u);
+        }
+        if (lane == 63) pc.wsum[w] = inc;
+        __syncthreads();
+        int carry = __shfl_up(inc, 1);
+        if (lane == 0) carry = 0;
+        for (int k = 0; k < w; ++k) carry = max(carry, pc.wsum[k]);
+        for (int j = j0; j < j1; ++j) {
+            carry = max(carry, SC[j]);
+            SC[j] = carry;
+        }
+        __syncthreads();
+    }
+    // stretches: a new one at every violation whose last cut differs from its
+    // predecessor's; at most PAVA_MAXC of them, evenly
+    {
+        const int fper = (nv + nt - 1) / nt;
+        const int f0 = tid * fper, f1 = min(f0 + fper, nv);
         int cnt = 0;
-        for (int f = f0; f < f1; ++f) cnt += (f == 0 || vio[f] - vio[f - 1] >= 3) ? 1 : 0;
+        for (int f = f0; f < f1; ++f) cnt += (f == 0 || SC[vio[f]] != SC[vio[f - 1]]) ? 1 : 0;
         int inc = cnt;
         for (int off = 1; off < 64; off <<= 1) {
             const int t = __shfl_up(inc, off);
@@ -305,14 +363,15 @@ __device__ inline void pava_block_chunked(double *v, int L, const int *vio, int 
         }
         const int stride = (total + PAVA_MAXC - 1) / PAVA_MAXC;
         for (int f = f0; f < f1; ++f)
-            if (f == 0 || vio[f] - vio[f - 1] >= 3) {
+            if (f == 0 || SC[vio[f]] != SC[vio[f - 1]]) {
                 if (base % stride == 0) {
                     const int k = base / stride;
                     pc.fv[k] = f;
-                    pc.cb[k] = f == 0 ? 0 : (vio[f - 1] + vio[f] + 2) >> 1;
+                    pc.cb[k] = f == 0 ? 0 : SC[vio[f]];
                 }
                 ++base;
             }
+        __syncthreads();
         if (tid == 0) {
             const int nc = (total + stride - 1) / stride;
             pc.nc = nc;

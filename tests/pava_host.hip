@@ -1,6 +1,7 @@
 // Host harness for the library's sparse pool-adjacent-violators pass (the
 // same source the kernels inline), used by the CPU tests to compare it bit
 // for bit with the oracle's stack form.
+#include <algorithm>
 #include <vector>
 
 #include "pr_coarse_dev.hpp"
@@ -23,21 +24,27 @@ extern "C" int pv_pava_sparse(double *v, int L) {
     return np;
 }
 
-// The stretch decomposition of the block pass, run serially: violations
-// grouped into clusters (neighbours less than three apart), stretches cut
-// halfway between clusters, each stretch by pava_sparse_range, cuts that the
-// serial pass would cross dropped until none is.  Returns the rounds.
+// The stretch decomposition of the block pass, run serially: the input cut
+// where every value before is below every value after, each stretch holding
+// violations by pava_sparse_range, cuts that the serial pass would cross
+// dropped until none is.  Returns the rounds.
 extern "C" int pv_pava_stretches(double *v, int L) {
     std::vector<int> vio;
     for (int j = 0; j + 1 < L; ++j)
         if (v[j] > v[j + 1]) vio.push_back(j);
     const int nv = (int)vio.size();
     if (nv == 0) return 0;
+    // cuts: max(v[0..b)) < min(v[b..L)); last cut at or before every position
+    std::vector<double> pm(L), sm(L);
+    for (int j = 0; j < L; ++j) pm[j] = j ? std::max(pm[j - 1], v[j]) : v[j];
+    for (int j = L - 1; j >= 0; --j) sm[j] = j + 1 < L ? std::min(sm[j + 1], v[j]) : v[j];
+    std::vector<int> last(L, 0);
+    for (int b = 1; b < L; ++b) last[b] = pm[b - 1] < sm[b] ? b : last[b - 1];
     std::vector<int> cb, fv;
     for (int f = 0; f < nv; ++f)
-        if (f == 0 || vio[f] - vio[f - 1] >= 3) {
+        if (f == 0 || last[vio[f]] != last[vio[f - 1]]) {
             fv.push_back(f);
-            cb.push_back(f == 0 ? 0 : (vio[f - 1] + vio[f] + 2) >> 1);
+            cb.push_back(f == 0 ? 0 : last[vio[f]]);
         }
     cb.push_back(L);
     fv.push_back(nv);
