@@ -115,10 +115,26 @@ __device__ inline void masses_to_knots_block(const double *rho, double *C, const
     }
 }
 
-// Pool-adjacent-violators (equal weights) with the same additions, divisions
-// and comparisons as the textbook stack form: a new value starts a pool (sum
-// s, count c); while the pool below has a larger mean S/C it is merged
-// (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
+// Whether the rounded mean a/ca exceeds the rounded mean b/cb (counts >= 1).
+// Where the cross products a*cb and b*ca differ by more than 2^-49 of their
+// magnitudes (plus 2^-1000), the exact means differ by more than 2^-50 of
+// theirs, more than the two roundings of the divisions can close, so the
+// rounded means compare as the exact ones do; otherwise (and for inf or NaN)
+// both divisions are taken and compared.  The result is that of comparing
+// the two rounded quotients in every case.
+__host__ __device__ inline bool mean_above(double a, int ca, double b, int cb) {
+#pragma clang fp contract(off)
+    const double x = a * (double)cb, y = b * (double)ca;
+    const double d = x - y, tol = (fabs(x) + fabs(y)) * 0x1p-49 + 0x1p-1000;
+    if (d > tol) return true;
+    if (-d > tol) return false;
+    return a / (double)ca > b / (double)cb;
+}
+
+// Pool-adjacent-violators (equal weights) with the same additions and the
+// same outcome of every comparison as the textbook stack form: a new value
+// starts a pool (sum s, count c); while the pool below has a larger rounded
+// mean S/C it is merged (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
 // SC = start << 16 | count, in position order); a pool of one value is read
 // back from v.  When the pool on top is a single value, nothing merges until
 // the next violation v[j] > v[j+1] of the input (vio, increasing): the
@@ -129,7 +145,7 @@ __host__ __device__ inline void pava_sparse(const double *v, int L, const int *v
 #pragma clang fp contract(off)
     int nb = 0, vi = 0;
     int i = vio[0];
-    double tS = v[i], tM = tS;
+    double tS = v[i];
     int tC = 1, tSt = i;
     ++i;
     while (i < L) {
@@ -140,32 +156,34 @@ __host__ __device__ inline void pava_sparse(const double *v, int L, const int *v
             if (jn > i - 1) {
                 tSt = jn;
                 tS = v[jn];
-                tM = tS;
                 i = jn + 1;
             }
         }
-        double s = v[i], m = s;
+        double s = v[i];
         int c = 1, st = i;
         bool below = true;
-        while (below && tM > m) {
+        while (below && mean_above(tS, tC, s, c)) {
             s = s + tS;
             c = c + tC;
             st = tSt;
             if (tSt == 0) {
                 below = false;
-            } else if (nb > 0 && (SC[nb - 1] >> 16) + (SC[nb - 1] & 0xFFFF) == tSt) {
-                --nb;
-                tS = S[nb];
-                tC = SC[nb] & 0xFFFF;
-                tSt = SC[nb] >> 16;
-                tM = tS / (double)tC;
             } else {
-                tSt = tSt - 1;
-                tS = v[tSt];
-                tC = 1;
-                tM = tS / 1.0;
+                // both candidates for the next pool down, loaded together
+                const int k = nb > 0 ? nb - 1 : 0;
+                const int sc = SC[k];
+                const double sv = S[k], vv = v[tSt - 1];
+                if (nb > 0 && (sc >> 16) + (sc & 0xFFFF) == tSt) {
+                    --nb;
+                    tS = sv;
+                    tC = sc & 0xFFFF;
+                    tSt = sc >> 16;
+                } else {
+                    tSt = tSt - 1;
+                    tS = vv;
+                    tC = 1;
+                }
             }
-            m = s / (double)c;
         }
         if (below && tC > 1) {
             S[nb] = tS;
@@ -175,7 +193,6 @@ __host__ __device__ inline void pava_sparse(const double *v, int L, const int *v
         tS = s;
         tC = c;
         tSt = st;
-        tM = m;
         ++i;
     }
     if (tC > 1) {
@@ -199,7 +216,7 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
     int nb = 0, vi = 0;
     double fmin_ = v[lo];
     int i = vio[0];
-    double tS = v[i], tM = tS;
+    double tS = v[i];
     int tC = 1, tSt = i;
     ++i;
     while (i < hi) {
@@ -210,33 +227,37 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
             if (jn > i - 1) {
                 tSt = jn;
                 tS = v[jn];
-                tM = tS;
                 i = jn + 1;
             }
         }
-        double s = v[i], m = s;
+        double s = v[i];
         int c = 1, st = i;
         bool below = true;
-        while (below && tM > m) {
+        while (below && mean_above(tS, tC, s, c)) {
             s = s + tS;
             c = c + tC;
             st = tSt;
             if (tSt == lo) {
                 below = false;
-            } else if (nb > 0 && (SC[lo + nb - 1] >> 16) + (SC[lo + nb - 1] & 0xFFFF) == tSt) {
-                --nb;
-                tS = S[lo + nb];
-                tC = SC[lo + nb] & 0xFFFF;
-                tSt = SC[lo + nb] >> 16;
-                tM = tS / (double)tC;
             } else {
-                tSt = tSt - 1;
-                tS = v[tSt];
-                tC = 1;
-                tM = tS / 1.0;
+                const int k = lo + (nb > 0 ? nb - 1 : 0);
+                const int sc = SC[k];
+                const double sv = S[k], vv = v[tSt - 1];
+                if (nb > 0 && (sc >> 16) + (sc & 0xFFFF) == tSt) {
+                    --nb;
+                    tS = sv;
+                    tC = sc & 0xFFFF;
+                    tSt = sc >> 16;
+                } else {
+                    tSt = tSt - 1;
+                    tS = vv;
+                    tC = 1;
+                }
             }
-            m = s / (double)c;
-            if (st == lo && m < fmin_) fmin_ = m;
+            if (st == lo) {
+                const double m = s / (double)c;
+                if (m < fmin_) fmin_ = m;
+            }
         }
         if (below && tC > 1) {
             S[lo + nb] = tS;
@@ -246,10 +267,9 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
         tS = s;
         tC = c;
         tSt = st;
-        tM = m;
         ++i;
     }
-    *lm = (i - 1 == hi - 1) ? tM : v[hi - 1];
+    *lm = (i - 1 == hi - 1) ? tS / (double)tC : v[hi - 1];
     if (tC > 1) {
         S[lo + nb] = tS;
         SC[lo + nb] = (tSt << 16) | tC;

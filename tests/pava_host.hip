@@ -6,6 +6,12 @@
 
 #include "pr_coarse_dev.hpp"
 
+// The library's comparison of two pool means, over arrays: out[i] = 1 when
+// a[i]/ca[i] > b[i]/cb[i] as the library decides it.
+extern "C" void pv_mean_above(const double *a, const int *ca, const double *b, const int *cb, int n, int *out) {
+    for (int i = 0; i < n; ++i) out[i] = pr::mean_above(a[i], ca[i], b[i], cb[i]) ? 1 : 0;
+}
+
 // v[0..L) in place; returns the number of pools of more than one value.
 extern "C" int pv_pava_sparse(double *v, int L) {
     std::vector<int> vio;

@@ -98,6 +98,35 @@ def test_fine_propagate_all_slices(torch_dev, d, n, S, K, dt, eps):
         assert np.abs(yg[k] - yr).max() < 1e-12 * max(1.0, np.abs(yr).max()), k
 
 
+def test_fine_large_workload_sampled(torch_dev):
+    """The large workload's launch (P = 2^20, all 64 slices of 1e5 steps of
+    dt = 1e-4 in one launch, 2 particles per thread), each slice from its own
+    start state, against the oracle on 32 particles of every slice (the last
+    32 of the last slice included)."""
+    torch = torch_dev
+    cfg = inputs.CFG_LARGE
+    n, K = cfg["n"], cfg["K"]
+    S = int(round(cfg["T"] / cfg["dt"]))
+    dt = cfg["T"] / S
+    _say(f"fine large n={n} K={K} S={S}")
+    so = OP.Sde(lam=cfg["lam"], eps=cfg["eps"], beta=cfg["beta"])
+    x0, y0 = OP.init_ensemble(so, 0, 0, n)
+    x = torch.from_numpy(np.stack([x0 + 0.01 * k for k in range(K)])).cuda()
+    y = torch.from_numpy(np.stack([y0[0] - 0.01 * k for k in range(K)])).cuda()
+    pr.pr_fine_propagate(pr.Sde(lam=cfg["lam"], eps=cfg["eps"], beta=cfg["beta"]), pr.Schedule(S, K, dt), 0, 0, n,
+                         0, K, x, y)
+    _sync(torch)
+    b = OI.slice_bounds(S, K)
+    for k in range(K):
+        p0 = n - 32 if k == K - 1 else (k * 16_381) % (n - 32)
+        xg = x[k, p0:p0 + 32].cpu().numpy()
+        yg = y[k, p0:p0 + 32].cpu().numpy()
+        xr, yr = OP.em_propagate(so, 0, 0, x0[p0:p0 + 32] + 0.01 * k, y0[:, p0:p0 + 32] - 0.01 * k, b[k], b[k + 1],
+                                 dt, p0=p0)
+        assert np.abs(xg - xr).max() < 1e-12 * max(1.0, np.abs(xr).max()), k
+        assert np.abs(yg - yr[0]).max() < 1e-12 * max(1.0, np.abs(yr).max()), k
+
+
 def test_fine_subrange_and_in_place(torch_dev):
     """Slices [2, 4) of a 5-slice schedule on their own give the same numbers
     as inside a full launch (counter-based noise keyed by the global step)."""
@@ -360,5 +389,43 @@ def test_parareal_exactness_bitwise(torch_dev, flags):
                 assert np.array_equal(xg[t], ref[t].cpu().numpy()), (k, t)
         assert errs[-1] == 0.0 and errs[-2] == 0.0
         assert pr.pr_parareal_iteration(h) == K
+    finally:
+        pr.pr_parareal_destroy(h)
+
+
+def test_parareal_large_workload_iteration(torch_dev):
+    """The large workload as the benchmark runs it (P = 2^20, 64 slices of
+    1e5 steps, 1024 cells, 100 levels): after one iteration the state at t_1
+    is the fine propagation of X0 bitwise and its knots are the serial run's
+    exactly (Sec. 3.3.3); every state's knots are non-decreasing,
+    start and end at the state's extremes and agree with the Hazen knots the
+    oracle takes of the same state."""
+    torch = torch_dev
+    cfg = inputs.CFG_LARGE
+    n, K, nq = cfg["n"], cfg["K"], cfg["nq"]
+    _say(f"parareal large n={n} K={K}")
+    h, sde, sched = _gpu_parareal(torch, cfg)
+    try:
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        pr.pr_init_ensemble(sde, 0, 0, n, x, y)
+        qref = torch.zeros((K + 1, nq + 1), dtype=torch.float64, device="cuda")
+        ws = torch.empty(pr.pr_restrict_workspace_size(n, 1), dtype=torch.uint8, device="cuda")
+        pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, nq, qref[0], ws)
+        pr.pr_fine_propagate(sde, sched, 0, 0, n, 0, 1, x, y)
+        pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, nq, qref[1], ws)
+        errs = np.zeros(2)
+        pr.pr_parareal_iterate(h, 1, q_ref=qref, err_out=errs)
+        xs = torch.empty(n, dtype=torch.float64, device="cuda")
+        q = torch.empty(nq + 1, dtype=torch.float64, device="cuda")
+        pr.pr_parareal_state(h, 1, x=xs, q=q)
+        assert torch.equal(xs, x)
+        assert torch.equal(q, qref[1])
+        for t in (2, K // 2, K):
+            pr.pr_parareal_state(h, t, x=xs, q=q)
+            xn, qn = xs.cpu().numpy(), q.cpu().numpy()
+            assert np.all(np.diff(qn) >= 0.0), t
+            assert qn[0] == xn.min() and qn[-1] == xn.max(), t
+            assert np.array_equal(qn, OR.hazen_knots(np.sort(xn), nq)), t
     finally:
         pr.pr_parareal_destroy(h)

@@ -31,6 +31,8 @@ def pv():
     L.pv_pava_sparse.restype = ctypes.c_int
     L.pv_pava_stretches.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.pv_pava_stretches.restype = ctypes.c_int
+    L.pv_mean_above.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p]
+    L.pv_mean_above.restype = None
     return L
 
 
@@ -56,9 +58,17 @@ def _cases():
     for c0 in (200, 900, 1500, 2600):
         w[c0:c0 + 60:2] += 3.0
     yield w
+    # near ties: runs of one value moved by a few units in the last place,
+    # so that neighbouring pool means differ only in their rounding
+    base = np.repeat(np.round(rng.random(80), 2), 6)
+    yield base + rng.integers(-3, 4, base.size) * np.spacing(base)
+    # pools of many thirds and tenths, whose sums round
+    t = np.repeat(np.arange(1, 40) / 3.0, 7)[::-1].copy()
+    t[::5] += 0.1
+    yield t
 
 
-@pytest.mark.parametrize("case", list(range(11)))
+@pytest.mark.parametrize("case", list(range(13)))
 def test_sparse_pava_is_the_stack_form_bitwise(pv, case):
     v = list(_cases())[case].astype(np.float64)
     ref = OI.pava(v.copy())
@@ -67,7 +77,7 @@ def test_sparse_pava_is_the_stack_form_bitwise(pv, case):
     assert np.array_equal(got, np.asarray(ref)), np.abs(got - ref).max()
 
 
-@pytest.mark.parametrize("case", list(range(11)))
+@pytest.mark.parametrize("case", list(range(13)))
 def test_stretch_decomposition_is_the_stack_form_bitwise(pv, case):
     """The stretches of the block pass, each on its own, with the cuts that
     the serial pass would cross dropped: the stack form's result bit for bit."""
@@ -91,3 +101,35 @@ def test_stretch_decomposition_on_random_walks(pv):
         rounds.append(pv.pv_pava_stretches(got.ctypes.data_as(ctypes.c_void_p), n))
         assert np.array_equal(got, ref), (t, np.abs(got - ref).max())
     assert max(rounds) >= 1
+
+
+def test_mean_comparison_is_that_of_the_rounded_quotients(pv):
+    """The library decides S/C > S'/C' from cross products where they are
+    far apart and from the quotients otherwise: on near ties (means equal in
+    exact arithmetic, or a few units in the last place apart), wide
+    magnitudes, zeros, infinities and NaN it answers as the comparison of
+    the two rounded quotients does."""
+    rng = np.random.default_rng(23)
+    n = 200_000
+    ca = rng.integers(1, 65536, n).astype(np.int32)
+    cb = rng.integers(1, 65536, n).astype(np.int32)
+    mean = rng.normal(0.0, 1.0, n) * 10.0 ** rng.integers(-300, 300, n)
+    kind = rng.integers(0, 4, n)
+    with np.errstate(over="ignore"):
+        a = mean * ca
+        near = (mean + rng.integers(-4, 5, n) * np.spacing(mean)) * cb
+        b = np.where(kind == 0, mean * cb,                  # ties in exact arithmetic
+                     np.where(kind == 1, near, np.where(kind == 2, rng.normal(0.0, 1.0, n) * cb, -a * cb / ca)))
+    a[:8] = [0.0, -0.0, np.inf, -np.inf, np.nan, 1.0, 5e-324, -5e-324]
+    b[:8] = [-0.0, 0.0, np.inf, 1.0, 1.0, np.nan, 0.0, 5e-324]
+    out = np.zeros(n, dtype=np.int32)
+    p = lambda z: np.ascontiguousarray(z).ctypes.data_as(ctypes.c_void_p)
+    a, b = np.ascontiguousarray(a), np.ascontiguousarray(b)
+    pv.pv_mean_above(p(a), p(ca), p(b), p(cb), n, p(out))
+    with np.errstate(invalid="ignore", over="ignore"):
+        ref = (a / ca.astype(np.float64)) > (b / cb.astype(np.float64))
+    assert np.array_equal(out.astype(bool), ref)
+    # the near ties do reach the quotients: their rounded means are equal or
+    # a few units apart, both outcomes occurring
+    close = (kind == 1) | (kind == 0)
+    assert ref[close].any() and (~ref[close]).any()
