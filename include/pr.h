@@ -186,6 +186,28 @@ int pr_match_quantiles(const double *q_target, const double *q_prior, const uint
                        int precision, void *stream);
 
 /*
+ * Knots (Sec. 4.4, midpoint convention) of the matched ensembles without
+ * sorting them.  For the k ensembles X that pr_match_quantiles(q_target,
+ * q_prior, rank, n, k, n_q, x_prior, ...) makes from the priors, q_out
+ * (device, [k][n_q+1]) receives the knots that pr_restrict_quantiles of X
+ * would give, bit for bit: matching moves every prior value by a smooth
+ * function of its rank, so the matched values in the prior's rank order are
+ * nearly sorted, and every order statistic the knots need is found between
+ * the nearest positions before and after its rank where all values before
+ * lie below all values after.  ws, ws_bytes: the workspace of the
+ * pr_restrict_quantiles call on x_prior that produced rank (same n, k,
+ * precision), not used since; its sorted keys are read and the rest of its
+ * key storage is overwritten.  flag (device, one int) is set to 1, else 0,
+ * where some order statistic could not be isolated (matched values far from
+ * the prior's order): q_out is then incomplete and the knots are to be
+ * taken by pr_restrict_quantiles of X.  Returns PR_E_UNSUPPORTED, launching
+ * nothing, when n is too small for the workspace to hold the chunk extremes
+ * (2 keys per 64 particles).
+ */
+int pr_match_knots(const double *q_target, const double *q_prior, int64_t n, int k, int n_q,
+                   int precision, void *ws, size_t ws_bytes, double *q_out, int *flag, void *stream);
+
+/*
  * Coarse propagator C (Sec. 2.2): finite volumes for the slow Fokker-Planck
  * equation eq. (FPz) with the effective drift of eq. (Fbar),
  * V' = c3 x^3 + (c1 + lambda (1 - mean a)) x, Dbar = 1/beta, zero flux at the
@@ -225,6 +247,11 @@ int pr_parareal_create(const pr_sde *sde, const pr_schedule *sched, const pr_gri
 int pr_parareal_iterate(void *h, int n_iter, const double *q_ref, double *err_out, void *stream);
 int pr_parareal_state(void *h, int t, void *x, void *y, double *q, void *stream);
 int pr_parareal_iteration(const void *h);
+/* Iterations since creation whose new knots were taken by a sort of the new
+ * states (when pr_match_knots could not isolate them), or -1 for h NULL.
+ * pr_parareal_iterate waits for its stream once per iteration to decide
+ * this. */
+int pr_parareal_knot_sorts(const void *h);
 /* With PR_PROFILE: ms_out (host, PR_PH_COUNT doubles) receives the summed
  * device time of each phase over all iterations since creation, measured by
  * HIP events recorded on the iteration's stream; iterations (host, may be

@@ -13,11 +13,11 @@ import os
 __all__ = [
     "Sde", "Schedule", "Grid", "PrError", "lib", "available",
     "pr_version", "pr_last_error", "pr_draw_coupling", "pr_init_ensemble", "pr_fine_propagate",
-    "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles",
+    "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles", "pr_match_knots",
     "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy",
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
-    "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE", "PR_SKIP_CONVERGED",
-    "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
+    "pr_parareal_knot_sorts", "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE",
+    "PR_SKIP_CONVERGED", "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
     "pr_adjoint_workspace_size", "pr_fine_adjoint", "pr_draw_instances", "pr_parareal_batch_create",
     "pr_parareal_batch_iterate", "pr_parareal_batch_state", "pr_parareal_batch_info", "pr_parareal_batch_destroy",
     "PR_AUTOTUNE", "PR_LAUNCH_BATCHED", "PR_LAUNCH_GRAPH", "PR_LAUNCH_PER_INSTANCE",
@@ -136,6 +136,7 @@ _SIGS = {
     "pr_restrict_quantiles": (_c_int, [_vp, _c_int, _c_i64, _c_int, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "pr_match_quantiles": (_c_int, [_vp, _vp, _vp, _c_i64, _c_int, _c_int, _vp, _vp, _c_int, _vp]),
+    "pr_match_knots": (_c_int, [_vp, _vp, _c_i64, _c_int, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     "pr_coarse_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid), _vp,
                                   ctypes.POINTER(_vp)]),
     "pr_coarse_fp_step": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
@@ -146,6 +147,7 @@ _SIGS = {
     "pr_parareal_iterate": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
     "pr_parareal_state": (_c_int, [_vp, _c_int, _vp, _vp, _vp, _vp]),
     "pr_parareal_iteration": (_c_int, [_vp]),
+    "pr_parareal_knot_sorts": (_c_int, [_vp]),
     "pr_parareal_destroy": (_c_int, [_vp]),
     "pr_parareal_profile": (_c_int, [_vp, ctypes.POINTER(_c_dbl), ctypes.POINTER(_c_int)]),
     "pr_fine_checkpoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64,
@@ -278,6 +280,12 @@ def pr_match_quantiles(q_target, q_prior, rank, n, k, n_q, x_prior, x_out, preci
                                     _ptr(x_out), precision, _stream(stream)))
 
 
+def pr_match_knots(q_target, q_prior, n, k, n_q, ws, q_out, flag, precision=PR_F64, stream=None):
+    nbytes = ws.numel() * ws.element_size()
+    _check(lib().pr_match_knots(_ptr(q_target), _ptr(q_prior), n, k, n_q, precision, _ptr(ws), nbytes, _ptr(q_out),
+                                _ptr(flag), _stream(stream)))
+
+
 def pr_coarse_create(sde, sched, grid, stream=None):
     h = _vp()
     s, c, g = sde.c(), sched.c(), grid.c()
@@ -323,6 +331,10 @@ def pr_parareal_state(h, t, x=None, y=None, q=None, stream=None):
 
 def pr_parareal_iteration(h):
     return lib().pr_parareal_iteration(h)
+
+
+def pr_parareal_knot_sorts(h):
+    return lib().pr_parareal_knot_sorts(h)
 
 
 def pr_parareal_destroy(h):

@@ -131,142 +131,109 @@ __host__ __device__ inline bool mean_above(double a, int ca, double b, int cb) {
     return a / (double)ca > b / (double)cb;
 }
 
-// Pool-adjacent-violators (equal weights) with the same additions and the
-// same outcome of every comparison as the textbook stack form: a new value
-// starts a pool (sum s, count c); while the pool below has a larger rounded
-// mean S/C it is merged (s = s + S, c = c + C).  Only pools of more than one value are stored (S and
-// SC = start << 16 | count, in position order); a pool of one value is read
-// back from v.  When the pool on top is a single value, nothing merges until
-// the next violation v[j] > v[j+1] of the input (vio, increasing): the
-// values in between stay single pools and are skipped.  One thread builds the
-// pools, the block then writes their means.
-__host__ __device__ inline void pava_sparse(const double *v, int L, const int *vio, int nv, double *S, int *SC,
-                                   int *npools) {
-#pragma clang fp contract(off)
-    int nb = 0, vi = 0;
-    int i = vio[0];
-    double tS = v[i];
-    int tC = 1, tSt = i;
-    ++i;
-    while (i < L) {
-        if (tC == 1) {
-            while (vi < nv && vio[vi] < i - 1) ++vi;
-            if (vi == nv) break;  // non-decreasing from v[i-1] on
-            const int jn = vio[vi];
-            if (jn > i - 1) {
-                tSt = jn;
-                tS = v[jn];
-                i = jn + 1;
-            }
-        }
-        double s = v[i];
-        int c = 1, st = i;
-        bool below = true;
-        while (below && mean_above(tS, tC, s, c)) {
-            s = s + tS;
-            c = c + tC;
-            st = tSt;
-            if (tSt == 0) {
-                below = false;
-            } else {
-                // both candidates for the next pool down, loaded together
-                const int k = nb > 0 ? nb - 1 : 0;
-                const int sc = SC[k];
-                const double sv = S[k], vv = v[tSt - 1];
-                if (nb > 0 && (sc >> 16) + (sc & 0xFFFF) == tSt) {
-                    --nb;
-                    tS = sv;
-                    tC = sc & 0xFFFF;
-                    tSt = sc >> 16;
-                } else {
-                    tSt = tSt - 1;
-                    tS = vv;
-                    tC = 1;
-                }
-            }
-        }
-        if (below && tC > 1) {
-            S[nb] = tS;
-            SC[nb] = (tSt << 16) | tC;
-            ++nb;
-        }
-        tS = s;
-        tC = c;
-        tSt = st;
-        ++i;
-    }
-    if (tC > 1) {
-        S[nb] = tS;
-        SC[nb] = (tSt << 16) | tC;
-        ++nb;
-    }
-    *npools = nb;
-}
-
-// The sparse pass on the stretch [lo, hi) alone (vio: the violations inside
-// it, increasing; positions absolute): as if the stretch started the input.
-// Pools of more than one value go to S[lo + k], SC[lo + k].  Returns their
-// number; *fm receives the smallest of the means that the pool holding lo
-// takes (v[lo] first, then after every merge that reaches lo): the values the
-// serial pass over the whole input would compare with the mean of the last
-// pool before the stretch.  *lm receives the mean of the pool holding hi - 1.
+// Pool-adjacent-violators (equal weights) over the stretch [lo, hi) of v
+// alone, as if it started the input, with the same additions and the same
+// outcome of every comparison as the textbook stack form: a new value starts
+// a pool (sum s, count c); while the pool below has a larger rounded mean
+// S/C it is merged (s = s + S, c = c + C).  vio: the violations v[j] >
+// v[j+1] inside the stretch, increasing (positions absolute, at least one).
+//
+// The pool on top (T) and the pool just below it (B) are held in registers;
+// of the pools under T only those of more than one value are stored, in
+// position order, at S[lo + k] and SC[lo + k] = start << 16 | count (B, when
+// it has more than one value, is the last of them); a pool of one value is
+// read back from v.  A run of values that each merge into T (a decreasing
+// run) thus touches only v.  When T is a single value, nothing merges until
+// the next violation: the values in between stay single pools and are
+// skipped.  Returns the number of stored pools.  *fm receives the smallest
+// of the means that the pool holding lo takes (v[lo] first, then after
+// every merge that reaches lo): the values the serial pass over a longer
+// input would compare with the mean of the last pool before the stretch.
+// *lm receives the mean of the pool holding hi - 1.
 __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi, const int *vio, int nv,
                                                  double *S, int *SC, double *fm, double *lm) {
 #pragma clang fp contract(off)
     int nb = 0, vi = 0;
     double fmin_ = v[lo];
     int i = vio[0];
-    double tS = v[i];
-    int tC = 1, tSt = i;
+    double tS = v[i], bS = 0.0;
+    int tC = 1, tSt = i, bC = 1, bSt = i - 1;
+    if (i > lo) bS = v[i - 1];
     ++i;
+    double vcur = v[i < hi ? i : hi - 1];
     while (i < hi) {
         if (tC == 1) {
-            while (vi < nv && vio[vi] < i - 1) ++vi;
-            if (vi == nv) break;
+            // first violation at or after i - 1 (binary search: a decreasing
+            // run leaves a long stretch of consumed ones behind)
+            int lo2 = vi, hi2 = nv;
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2) >> 1;
+                if (vio[mid] < i - 1) lo2 = mid + 1;
+                else hi2 = mid;
+            }
+            vi = lo2;
+            if (vi == nv) break;  // non-decreasing from v[i-1] on
             const int jn = vio[vi];
             if (jn > i - 1) {
                 tSt = jn;
                 tS = v[jn];
+                bSt = jn - 1;  // a single value: the values since i - 1 stay single
+                bS = v[jn - 1];
+                bC = 1;
                 i = jn + 1;
+                vcur = v[i];
             }
         }
-        double s = v[i];
+        double s = vcur;
+        vcur = v[i + 1 < hi ? i + 1 : i];  // the next value, loaded ahead
         int c = 1, st = i;
-        bool below = true;
-        while (below && mean_above(tS, tC, s, c)) {
+        if (mean_above(tS, tC, s, c)) {
             s = s + tS;
             c = c + tC;
             st = tSt;
-            if (tSt == lo) {
-                below = false;
-            } else {
-                const int k = lo + (nb > 0 ? nb - 1 : 0);
-                const int sc = SC[k];
-                const double sv = S[k], vv = v[tSt - 1];
-                if (nb > 0 && (sc >> 16) + (sc & 0xFFFF) == tSt) {
-                    --nb;
-                    tS = sv;
-                    tC = sc & 0xFFFF;
-                    tSt = sc >> 16;
-                } else {
-                    tSt = tSt - 1;
-                    tS = vv;
-                    tC = 1;
-                }
-            }
             if (st == lo) {
                 const double m = s / (double)c;
                 if (m < fmin_) fmin_ = m;
             }
+            while (st != lo && mean_above(bS, bC, s, c)) {
+                s = s + bS;
+                c = c + bC;
+                st = bSt;
+                if (bC > 1) --nb;  // B was the last stored pool
+                if (st == lo) {
+                    const double m = s / (double)c;
+                    if (m < fmin_) fmin_ = m;
+                } else {
+                    const int k = lo + (nb > 0 ? nb - 1 : 0);
+                    const int sc = SC[k];
+                    const double sv = S[k], vv = v[st - 1];
+                    if (nb > 0 && (sc >> 16) + (sc & 0xFFFF) == st) {
+                        bS = sv;
+                        bC = sc & 0xFFFF;
+                        bSt = sc >> 16;
+                    } else {
+                        bS = vv;
+                        bC = 1;
+                        bSt = st - 1;
+                    }
+                }
+            }
+            tS = s;
+            tC = c;
+            tSt = st;
+        } else {
+            if (tC > 1) {
+                S[lo + nb] = tS;
+                SC[lo + nb] = (tSt << 16) | tC;
+                ++nb;
+            }
+            bS = tS;
+            bC = tC;
+            bSt = tSt;
+            tS = s;
+            tC = 1;
+            tSt = i;
         }
-        if (below && tC > 1) {
-            S[lo + nb] = tS;
-            SC[lo + nb] = (tSt << 16) | tC;
-            ++nb;
-        }
-        tS = s;
-        tC = c;
-        tSt = st;
         ++i;
     }
     *lm = (i - 1 == hi - 1) ? tS / (double)tC : v[hi - 1];
@@ -277,6 +244,13 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
     }
     *fm = fmin_;
     return nb;
+}
+
+// The same pass over the whole input v[0..L).
+__host__ __device__ inline void pava_sparse(const double *v, int L, const int *vio, int nv, double *S, int *SC,
+                                            int *npools) {
+    double fm, lm;
+    *npools = pava_sparse_range(v, 0, L, vio, nv, S, SC, &fm, &lm);
 }
 
 // Pool-adjacent-violators over v[0..L) by the whole block from its known
@@ -298,6 +272,7 @@ struct PavaChunks {
     int cb[PAVA_MAXC + 1];  // stretch bounds
     int fv[PAVA_MAXC + 1];  // first violation of each stretch
     int np[PAVA_MAXC];      // stored pools of each stretch
+    int pst[PAVA_MAXC + 1];  // number of the first of them over all stretches
     double fm[PAVA_MAXC], lm[PAVA_MAXC];
     double wmax[16], wmin[16];
     int nc, drop, wsum[16];
@@ -445,15 +420,45 @@ __device__ inline void pava_block_chunked(double *v, int L, const int *vio, int 
         }
         __syncthreads();
     }
-    // write the means of the stored pools of every stretch
+    // write the means of the stored pools of every stretch, one wave per
+    // pool: the pools numbered through an exclusive scan of their counts
     const int nc = pc.nc;
-    for (int k = tid; k < nc; k += nt) {
-        const int lo = pc.cb[k];
-        for (int b = 0; b < pc.np[k]; ++b) {
-            const int cq = SC[lo + b] & 0xFFFF, st = SC[lo + b] >> 16;
-            const double mean = S[lo + b] / (double)cq;
-            for (int t = 0; t < cq; ++t) v[st + t] = mean;
+    {
+        const int per = (nc + nt - 1) / nt;
+        const int k0 = min(tid * per, nc), k1 = min(k0 + per, nc);
+        int cnt = 0;
+        for (int k = k0; k < k1; ++k) cnt += pc.np[k];
+        int inc = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
         }
+        if (lane == 63) pc.wsum[w] = inc;
+        __syncthreads();
+        int base = inc - cnt, total = 0;
+        for (int k = 0; k < nt / 64; ++k) {
+            if (k < w) base += pc.wsum[k];
+            total += pc.wsum[k];
+        }
+        for (int k = k0; k < k1; ++k) {
+            pc.pst[k] = base;
+            base += pc.np[k];
+        }
+        if (tid == 0) pc.pst[nc] = total;
+        __syncthreads();
+    }
+    const int total = pc.pst[nc], wl = min(64, nt - 64 * w);  // lanes of this wave
+    for (int g = w; g < total; g += (nt + 63) / 64) {
+        int a = 0, b = nc;  // the stretch holding pool g: pst[a] <= g < pst[b]
+        while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (pc.pst[mid] <= g) a = mid;
+            else b = mid;
+        }
+        const int idx = pc.cb[a] + (g - pc.pst[a]);
+        const int cq = SC[idx] & 0xFFFF, st = SC[idx] >> 16;
+        const double mean = S[idx] / (double)cq;
+        for (int t = lane; t < cq; t += wl) v[st + t] = mean;
     }
     __syncthreads();
 }
@@ -488,10 +493,11 @@ __device__ inline void pava_block(double *v, int L, double *S, int *SC, int *vio
     if (nbad == 0) return;
     if (threadIdx.x == 0) pava_sparse(v, L, vio, nbad, S, SC, &npools);
     __syncthreads();
-    for (int q = threadIdx.x; q < npools; q += nt) {
+    const int wl = min(64, nt - 64 * w);  // lanes of this wave
+    for (int q = w; q < npools; q += (nt + 63) / 64) {  // one wave per pool
         const int cq = SC[q] & 0xFFFF, st = SC[q] >> 16;
         const double mean = S[q] / (double)cq;
-        for (int t = 0; t < cq; ++t) v[st + t] = mean;
+        for (int t = lane; t < cq; t += wl) v[st + t] = mean;
     }
     __syncthreads();
 }

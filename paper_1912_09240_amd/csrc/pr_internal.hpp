@@ -168,6 +168,24 @@ __device__ __forceinline__ double value_of(uint32_t k) {
     return (double)__uint_as_float(b);
 }
 
+// Matching that preserves the fast marginal (Sec. 5.1, eq. (transformation))
+// of one particle: its prior value x at the mid-rank cdf value
+// u = (rank + 1/2)/P moved by the linear interpolant, at u, of the knot
+// differences dk = q_target - q_prior on the levels j/Q.  Every kernel that
+// needs a matched value calls this, so they agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T matched_value(T x, uint64_t rank, const double *dk, double nd, double Q) {
+#pragma clang fp contract(off)
+    const double u = ((double)rank + 0.5) / nd;
+    const double uq = u * Q;
+    double jf = floor(uq);
+    jf = jf < Q - 1.0 ? jf : Q - 1.0;
+    const int j = (int)jf;
+    const double w = uq - jf;
+    const double delta = (1.0 - w) * dk[j] + w * dk[j + 1];
+    return (T)((double)x + delta);
+}
+
 // ---------------------------------------------------------------------------
 // Internal entry points shared between translation units (no validation).
 // ---------------------------------------------------------------------------
@@ -187,6 +205,16 @@ struct MatchArgs {
     int64_t xout_stride;
 };
 int match_strided(const MatchArgs &a, int64_t n, int k, int nq, int precision, hipStream_t st);
+
+// Knots of the k matched ensembles X = M(Xbar) (n particles each, matched
+// with the knot rows qt, qp as by match_strided) straight from the sorted
+// keys that the last restrict_quantiles call on Xbar left in ws, without a
+// sort of X: *flag (device) is set where some order statistic could not be
+// isolated, and the knots are then to be taken by restrict_quantiles.
+// Returns PR_E_UNSUPPORTED (nothing launched) where ws has no room for the
+// chunk extremes.
+int matched_knots(const void *ws, int precision, int64_t n, int k, int nq, const double *qt, int64_t qt_stride,
+                  const double *qp, int64_t qp_stride, double *q, int *flag, hipStream_t st);
 
 // x_in/y_in and x_out/y_out may alias (in place).
 int fine_propagate(const pr_sde *sde, const pr_schedule *sch, uint64_t seed, uint32_t inst, int64_t n,

@@ -31,14 +31,7 @@ __global__ void __launch_bounds__(MT_THREADS) match_kernel(MatchArgs a, int64_t 
     for (int q = 0; q < MT_PPT; ++q) {
         const int64_t p = p0 + (int64_t)q * MT_THREADS;
         if (p >= n) break;
-        const double u = ((double)rank[p] + 0.5) / nd;
-        const double uq = u * Q;
-        double jf = floor(uq);
-        jf = jf < Q - 1.0 ? jf : Q - 1.0;
-        const int j = (int)jf;
-        const double w = uq - jf;
-        const double delta = (1.0 - w) * dk[j] + w * dk[j + 1];
-        xout[p] = (T)((double)xin[p] + delta);
+        xout[p] = matched_value<T>(xin[p], rank[p], dk, nd, Q);
     }
 }
 

@@ -39,10 +39,13 @@ struct Parareal {
     double *qcs = nullptr;   // [K+1][Q+1]  coarse results of the previous states
     uint32_t *rank = nullptr;  // [K][n] ranks of the fine results / of X0
     double *err = nullptr;   // [2]
+    int *flag = nullptr;     // set where the knots of the new states need a sort
+    int *flag_host = nullptr;  // pinned copy of it
     void *ws = nullptr;
     size_t ws_bytes = 0;
     int cur = 0;
     int k = 0;
+    int knot_sorts = 0;  // iterations whose new knots needed the sort
     hipEvent_t ev[PR_PH_COUNT + 1] = {};
     double ph_ms[PR_PH_COUNT] = {};
     int timed = 0;
@@ -59,6 +62,8 @@ static void parareal_free(Parareal *h) {
                     h->rank, h->err, h->ws};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (h->flag) (void)hipFree(h->flag);
+    if (h->flag_host) (void)hipHostFree(h->flag_host);
     for (hipEvent_t e : h->ev)
         if (e) (void)hipEventDestroy(e);
     delete h;
@@ -142,6 +147,9 @@ int parareal_create(const pr_sde *sde_in, const pr_schedule *sch, const pr_grid 
     PR_ALLOC(h->qcs, qb);
     PR_ALLOC(h->rank, sizeof(uint32_t) * (size_t)K * n);
     PR_ALLOC(h->err, sizeof(double) * 2);
+    PR_ALLOC(h->flag, sizeof(int));
+    PR_TRY(hipHostMalloc((void **)&h->flag_host, sizeof(int), hipHostMallocDefault) == hipSuccess ? PR_OK
+                                                                                                   : PR_E_NOMEM);
     h->ws_bytes = restrict_ws(n, K + 1, h->sde.precision);
     PR_ALLOC(h->ws, h->ws_bytes);
     PR_TRY(coarse_create(&h->sde, sch, grid, st, &h->coarse));
@@ -220,8 +228,22 @@ int parareal_iterate(Parareal *h, int n_iter, const double *q_ref, double *err_o
         PR_CHECK(match_strided(ma, n, K, Q, h->sde.precision, st));
         PR_CHECK(mark(5));
         std::swap(h->q, h->qn);
-        // 6. knots of the new states
-        PR_CHECK(restrict_states(h, nx, 1, K, st));
+        // 6. knots of the new states: order statistics of the matched values
+        // found from the fine results' sort (which the restriction left in
+        // the workspace), or a sort of the new states where that fails
+        const int mk = matched_knots(h->ws, h->sde.precision, n, K, Q, h->qrow(h->q, 1), Q + 1, h->qrow(h->qf, 1),
+                                     Q + 1, h->qrow(h->qR, 1), h->flag, st);
+        if (mk != PR_OK && mk != PR_E_UNSUPPORTED) return mk;
+        bool sort_new = mk == PR_E_UNSUPPORTED;
+        if (!sort_new) {
+            PR_HIP(hipMemcpyAsync(h->flag_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+            PR_HIP(hipStreamSynchronize(st));
+            sort_new = *h->flag_host != 0;
+        }
+        if (sort_new) {
+            PR_CHECK(restrict_states(h, nx, 1, K, st));
+            ++h->knot_sorts;
+        }
         h->cur = nx;
         h->k += 1;
         if (q_ref) {
@@ -287,6 +309,8 @@ extern "C" int pr_parareal_state(void *hv, int t, void *x, void *y, double *q, v
 }
 
 extern "C" int pr_parareal_iteration(const void *h) { return h ? ((const Parareal *)h)->k : -1; }
+
+extern "C" int pr_parareal_knot_sorts(const void *h) { return h ? ((const Parareal *)h)->knot_sorts : -1; }
 
 extern "C" int pr_parareal_profile(const void *hv, double *ms_out, int *iterations) {
     clear_error();

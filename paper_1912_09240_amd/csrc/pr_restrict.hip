@@ -417,6 +417,286 @@ __global__ void zero_u32(uint32_t *p, int64_t count) {
 }
 
 // ---------------------------------------------------------------------------
+// Knots of matched ensembles from the sort of their priors.
+//
+// Matching moves every prior value by a smooth function of its rank, so the
+// matched values taken in the prior's rank order, z_r = M(xs_r) (xs the
+// sorted prior), are nearly sorted.  A position c is a cut where every z
+// before it is below every z from it on, in key order (c = 0 and c = n are
+// cuts); between neighbouring cuts a <= r < b the order statistics of ranks
+// a..b-1 are z_a..z_{b-1} sorted.  The order statistic of rank r is thus the
+// key of rank r - a among the few values between the cuts around r.  The
+// maxima before and minima after every chunk of 64 ranks come from one
+// streaming pass and a scan; inside a chunk, from wave scans.
+// ---------------------------------------------------------------------------
+constexpr int MK_REACH = 8;  // chunks searched on either side of a rank for a cut
+
+template <typename K>
+__device__ __forceinline__ K shfl_key(K v, int src) {
+    return (K)__shfl((unsigned long long)v, src);
+}
+
+// Key of the matched value of the prior with key kp at rank r.
+template <typename K>
+__device__ __forceinline__ K matched_key(K kp, int64_t r, const double *dk, double nd, double Q) {
+    using V = typename KeyTraits<K>::V;
+    return key_of(matched_value<V>((V)value_of(kp), (uint64_t)r, dk, nd, Q));
+}
+
+template <typename K>
+__device__ __forceinline__ void load_dk(double *dk, const double *qt, int64_t qts, const double *qp, int64_t qps,
+                                        int seg, int nq) {
+    for (int j = threadIdx.x; j <= nq; j += blockDim.x) dk[j] = qt[seg * qts + j] - qp[seg * qps + j];
+    __syncthreads();
+}
+
+// Chunk and group extremes.  A group is 64 chunks (4096 ranks, one block of
+// 256 threads, 4 consecutive ranks per thread and pass).  For every chunk c
+// of group g: pre[c] = largest key of the chunks of g before c, suf[c] =
+// smallest key of the chunks of g from c on; gx[g], gn[g] = largest and
+// smallest key of g (turned into the values over the groups before g and
+// from g on by mk_scan).
+constexpr int MK_GROUP = 64;
+
+template <typename K>
+__global__ void __launch_bounds__(256) mk_extremes(const K *__restrict__ sorted_all, int64_t n, int64_t nch,
+                                                   int64_t ngr, const double *__restrict__ qt, int64_t qts,
+                                                   const double *__restrict__ qp, int64_t qps, int nq,
+                                                   K *__restrict__ pre, K *__restrict__ suf, K *__restrict__ gx,
+                                                   K *__restrict__ gn) {
+    extern __shared__ double dk[];
+    __shared__ K cx[MK_GROUP], cn[MK_GROUP];
+    const int seg = blockIdx.y;
+    load_dk<K>(dk, qt, qts, qp, qps, seg, nq);
+    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const K *sorted = sorted_all + seg * n;
+    const double nd = (double)n, Q = (double)nq;
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+        // ranks e0..e0+3 of chunk 16 w + 4 i + lane / 16 of the group
+        const int64_t e0 = g * (MK_GROUP * 64) + w * 1024 + i * 256 + 4 * lane;
+        K kx = 0, kn = ~(K)0;
+        K v[4];
+        if (e0 + 4 <= n) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = sorted[e0 + t];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const K z = matched_key<K>(v[t], e0 + t, dk, nd, Q);
+                kx = z > kx ? z : kx;
+                kn = z < kn ? z : kn;
+            }
+        } else {
+            for (int t = 0; t < 4; ++t)
+                if (e0 + t < n) {
+                    const K z = matched_key<K>(sorted[e0 + t], e0 + t, dk, nd, Q);
+                    kx = z > kx ? z : kx;
+                    kn = z < kn ? z : kn;
+                }
+        }
+        for (int off = 1; off < 16; off <<= 1) {  // over the 16 lanes of the chunk
+            const K ox = (K)__shfl_xor((unsigned long long)kx, off), on = (K)__shfl_xor((unsigned long long)kn, off);
+            kx = ox > kx ? ox : kx;
+            kn = on < kn ? on : kn;
+        }
+        if ((lane & 15) == 0) {
+            cx[w * 16 + i * 4 + (lane >> 4)] = kx;
+            cn[w * 16 + i * 4 + (lane >> 4)] = kn;
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        // lane = chunk of the group: exclusive prefix max, inclusive suffix min
+        const K x = cx[lane], m = cn[lane];
+        K px = x, sn = m;
+        for (int off = 1; off < 64; off <<= 1) {
+            const K u = shfl_key(px, lane >= off ? lane - off : lane);
+            const K d = shfl_key(sn, lane + off < 64 ? lane + off : lane);
+            px = u > px ? u : px;
+            sn = d < sn ? d : sn;
+        }
+        K ex = shfl_key(px, lane > 0 ? lane - 1 : 0);
+        if (lane == 0) ex = 0;
+        const int64_t c = g * MK_GROUP + lane;
+        if (c < nch) {
+            pre[seg * nch + c] = ex;
+            suf[seg * nch + c] = sn;
+        }
+        if (lane == 63) gx[seg * ngr + g] = px;
+        if (lane == 0) gn[seg * ngr + g] = sn;
+    }
+}
+
+// Per ensemble (one block of 256): gx[g] <- largest key of the groups before
+// g, gn[g] <- smallest key of the groups from g on.
+template <typename K>
+__global__ void __launch_bounds__(256) mk_scan(K *__restrict__ gx_all, K *__restrict__ gn_all, int64_t ngr) {
+    __shared__ K wmx[4], wmn[4];
+    K *gx = gx_all + blockIdx.x * ngr, *gn = gn_all + blockIdx.x * ngr;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t per = (ngr + 255) / 256;
+    const int64_t g0 = tid * per < ngr ? tid * per : ngr, g1 = g0 + per < ngr ? g0 + per : ngr;
+    K lx = 0, ln = ~(K)0;
+    for (int64_t g = g0; g < g1; ++g) {
+        lx = gx[g] > lx ? gx[g] : lx;
+        ln = gn[g] < ln ? gn[g] : ln;
+    }
+    K px = lx, sn = ln;
+    for (int off = 1; off < 64; off <<= 1) {
+        const K u = shfl_key(px, lane >= off ? lane - off : lane);
+        const K d = shfl_key(sn, lane + off < 64 ? lane + off : lane);
+        px = u > px ? u : px;
+        sn = d < sn ? d : sn;
+    }
+    if (lane == 63) wmx[w] = px;
+    if (lane == 0) wmn[w] = sn;
+    __syncthreads();
+    K ex = shfl_key(px, lane > 0 ? lane - 1 : 0);
+    if (lane == 0) ex = 0;
+    K es = shfl_key(sn, lane < 63 ? lane + 1 : 63);
+    if (lane == 63) es = ~(K)0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) ex = wmx[k] > ex ? wmx[k] : ex;
+        if (k > w) es = wmn[k] < es ? wmn[k] : es;
+    }
+    for (int64_t g = g0; g < g1; ++g) {
+        const K v = gx[g];
+        gx[g] = ex;
+        ex = v > ex ? v : ex;
+    }
+    for (int64_t g = g1 - 1; g >= g0; --g) {
+        es = gn[g] < es ? gn[g] : es;
+        gn[g] = es;
+    }
+}
+
+// The extremes one ensemble's cut tests read.
+template <typename K>
+struct MkExt {
+    const K *pre, *suf, *gx, *gn;
+    int64_t nch, ngr;
+    // largest key of the chunks before c
+    __device__ K before(int64_t c) const {
+        const K a = pre[c], b = gx[c / MK_GROUP];
+        return a > b ? a : b;
+    }
+    // smallest key of the chunks from c on (c <= nch)
+    __device__ K from(int64_t c) const {
+        if (c >= nch) return ~(K)0;
+        const int64_t g = c / MK_GROUP;
+        const K a = suf[c], b = g + 1 < ngr ? gn[g + 1] : ~(K)0;
+        return a < b ? a : b;
+    }
+};
+
+// Cut flags of the positions 64c + lane of chunk c (the wave).
+template <typename K>
+__device__ __forceinline__ uint64_t chunk_cuts(const K *sorted, int64_t n, const MkExt<K> &E, int64_t c,
+                                               const double *dk, double nd, double Q, int lane) {
+    const int64_t p = c * 64 + lane;
+    K kx = 0, kn = ~(K)0;
+    if (p < n) {
+        kx = matched_key<K>(sorted[p], p, dk, nd, Q);
+        kn = kx;
+    }
+    K px = kx, sn = kn;  // inclusive prefix max, inclusive suffix min inside the chunk
+    for (int off = 1; off < 64; off <<= 1) {
+        const K u = shfl_key(px, lane >= off ? lane - off : lane);
+        const K d = shfl_key(sn, lane + off < 64 ? lane + off : lane);
+        px = u > px ? u : px;
+        sn = d < sn ? d : sn;
+    }
+    K before = shfl_key(px, lane > 0 ? lane - 1 : 0);
+    if (lane == 0) before = 0;
+    const K b0 = E.before(c);
+    before = b0 > before ? b0 : before;
+    const K a0 = E.from(c + 1);
+    const K from = a0 < sn ? a0 : sn;
+    const bool cut = p == 0 || p == n || (p < n && before <= from);
+    return __ballot(cut);
+}
+
+// Key of the order statistic of rank r (the wave); sets *flag where the
+// cuts around r are not found within MK_REACH chunks or lie more than 64
+// ranks apart.
+template <typename K>
+__device__ K order_stat(const K *sorted, int64_t n, const MkExt<K> &E, int64_t r, const double *dk, double nd,
+                        double Q, int lane, int *flag) {
+    const int64_t nch = E.nch;
+    const int64_t c = r / 64;
+    const int off = (int)(r - c * 64);
+    const uint64_t mc = chunk_cuts<K>(sorted, n, E, c, dk, nd, Q, lane);
+    int64_t a = -1, b = -1;
+    uint64_t m = mc & (off == 63 ? ~0ull : ((2ull << off) - 1));  // positions <= r
+    if (m) a = c * 64 + 63 - __builtin_clzll(m);
+    for (int64_t cc = c - 1; a < 0 && cc >= 0 && cc >= c - MK_REACH; --cc) {
+        m = chunk_cuts<K>(sorted, n, E, cc, dk, nd, Q, lane);
+        if (m) a = cc * 64 + 63 - __builtin_clzll(m);
+    }
+    m = off == 63 ? 0ull : mc & ~((2ull << off) - 1);  // positions > r
+    if (m) b = c * 64 + __builtin_ctzll(m);
+    for (int64_t cc = c + 1; b < 0 && cc <= c + MK_REACH; ++cc) {
+        if (cc >= nch) {
+            b = n;
+            break;
+        }
+        m = chunk_cuts<K>(sorted, n, E, cc, dk, nd, Q, lane);
+        if (m) b = cc * 64 + __builtin_ctzll(m);
+    }
+    if (a < 0 || b < 0 || b - a > 64) {
+        if (lane == 0) *flag = 1;
+        return 0;
+    }
+    // rank r - a among z_a..z_{b-1}: count the smaller keys (ties by position)
+    const int ms = (int)(b - a);
+    const K w = lane < ms ? matched_key<K>(sorted[a + lane], a + lane, dk, nd, Q) : ~(K)0;
+    int below = 0;
+    for (int l = 0; l < ms; ++l) {
+        const K o = shfl_key(w, l);
+        below += (o < w || (o == w && l < lane)) ? 1 : 0;
+    }
+    const uint64_t sel = __ballot(lane < ms && below == (int)(r - a));
+    return shfl_key(w, __builtin_ctzll(sel));
+}
+
+// Midpoint (Hazen) knots of every matched ensemble, the arithmetic of
+// rs_knots on the order statistics: one wave per knot.
+template <typename K>
+__global__ void __launch_bounds__(256) mk_knots(const K *__restrict__ sorted_all, int64_t n, int64_t nch,
+                                                int64_t ngr, const double *__restrict__ qt, int64_t qts,
+                                                const double *__restrict__ qp, int64_t qps, int nq,
+                                                const K *__restrict__ pre, const K *__restrict__ suf,
+                                                const K *__restrict__ gx, const K *__restrict__ gn,
+                                                double *__restrict__ q, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+    extern __shared__ double dk[];
+    const int seg = blockIdx.y;
+    load_dk<K>(dk, qt, qts, qp, qps, seg, nq);
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j > nq) return;
+    const int lane = threadIdx.x & 63;
+    const K *sorted = sorted_all + seg * n;
+    const MkExt<K> E{pre + seg * nch, suf + seg * nch, gx + seg * ngr, gn + seg * ngr, nch, ngr};
+    const double nd = (double)n, Q = (double)nq;
+    const double t = (double)((int64_t)j * n) / (double)nq - 0.5;
+    double v;
+    if (t <= 0.0) {
+        v = value_of(order_stat<K>(sorted, n, E, 0, dk, nd, Q, lane, flag));
+    } else if (t >= (double)(n - 1)) {
+        v = value_of(order_stat<K>(sorted, n, E, n - 1, dk, nd, Q, lane, flag));
+    } else {
+        const int64_t r = (int64_t)floor(t);
+        const double f = t - (double)r;
+        const double a = value_of(order_stat<K>(sorted, n, E, r, dk, nd, Q, lane, flag));
+        const double b = value_of(order_stat<K>(sorted, n, E, r + 1, dk, nd, Q, lane, flag));
+        v = a + f * (b - a);
+        v = v < b ? v : b;
+    }
+    if (lane == 0) q[(int64_t)seg * (nq + 1) + j] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -531,6 +811,41 @@ int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t
                                      nullptr, ws, st);
 }
 
+
+template <typename K>
+static int matched_knots_impl(const void *ws, int64_t n, int k, int nq, const double *qt, int64_t qts,
+                              const double *qp, int64_t qps, double *q, int *flag, hipStream_t st) {
+    // the workspace as sort_impl lays it out: two key buffers, the sorted
+    // keys in the one the last pass wrote; the other is free scratch
+    char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    const size_t kb = align256((size_t)n * k * sizeof(K));
+    constexpr int last = (KeyTraits<K>::passes - 1) & 1;
+    const K *sorted = (const K *)(p + last * kb);
+    K *scratch = (K *)(p + (1 - last) * kb);
+    const int64_t nch = (n + 63) / 64, ngr = (nch + MK_GROUP - 1) / MK_GROUP;
+    if ((size_t)2 * (nch + ngr) * k * sizeof(K) > kb) return PR_E_UNSUPPORTED;
+    K *pre = scratch, *suf = pre + nch * k, *gx = suf + nch * k, *gn = gx + ngr * k;
+    const size_t lds = (size_t)(nq + 1) * sizeof(double);
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
+    PR_LAUNCHED();
+    hipLaunchKernelGGL(mk_extremes<K>, dim3((unsigned)ngr, (unsigned)k), dim3(256), lds, st, sorted, n, nch, ngr, qt,
+                       qts, qp, qps, nq, pre, suf, gx, gn);
+    PR_LAUNCHED();
+    hipLaunchKernelGGL(mk_scan<K>, dim3((unsigned)k), dim3(256), 0, st, gx, gn, ngr);
+    PR_LAUNCHED();
+    hipLaunchKernelGGL(mk_knots<K>, dim3((unsigned)((nq + 1 + 3) / 4), (unsigned)k), dim3(256), lds, st, sorted, n,
+                       nch, ngr, qt, qts, qp, qps, nq, (const K *)pre, (const K *)suf, (const K *)gx, (const K *)gn,
+                       q, flag);
+    PR_LAUNCHED();
+    return PR_OK;
+}
+
+int matched_knots(const void *ws, int precision, int64_t n, int k, int nq, const double *qt, int64_t qt_stride,
+                  const double *qp, int64_t qp_stride, double *q, int *flag, hipStream_t st) {
+    if (precision == PR_F64)
+        return matched_knots_impl<uint64_t>(ws, n, k, nq, qt, qt_stride, qp, qp_stride, q, flag, st);
+    return matched_knots_impl<uint32_t>(ws, n, k, nq, qt, qt_stride, qp, qp_stride, q, flag, st);
+}
 }  // namespace pr
 
 using namespace pr;
@@ -562,4 +877,23 @@ extern "C" int pr_restrict_quantiles(const void *x, int precision, int64_t n, in
     }
     return restrict_quantiles(x, precision, n, k, n_q, hist_grid, q, rank, perm, x_sorted, moments, hist, ws,
                               as_stream(stream));
+}
+
+extern "C" int pr_match_knots(const double *q_target, const double *q_prior, int64_t n, int k, int n_q,
+                              int precision, void *ws, size_t ws_bytes, double *q_out, int *flag, void *stream) {
+    clear_error();
+    PR_REQUIRE(valid_precision(precision), "precision must be 64 or 32");
+    PR_REQUIRE(n >= 1 && n <= 0xFFFFFFFFll, "n must be in [1, 2^32)");
+    PR_REQUIRE(k >= 1 && k <= 65535, "k must be in [1, 65535]");
+    PR_REQUIRE(n_q >= 1 && n_q <= 8191, "n_q must be in [1, 8191]");
+    PR_REQUIRE(q_target && q_prior && ws && q_out && flag, "pointers must be non-NULL");
+    if (ws_bytes < restrict_ws(n, k, precision)) {
+        set_error("workspace too small: %zu < %zu bytes", ws_bytes, restrict_ws(n, k, precision));
+        return PR_E_NOMEM;
+    }
+    const int rc = matched_knots(ws, precision, n, k, n_q, q_target, n_q + 1, q_prior, n_q + 1, q_out, flag,
+                                 as_stream(stream));
+    if (rc == PR_E_UNSUPPORTED) set_error("n = %lld is too small for the workspace to hold the chunk extremes",
+                                          (long long)n);
+    return rc;
 }

@@ -83,6 +83,17 @@ def test_validation_rejects_before_launch(lib):
                                 0, 10, 64, None, ctypes.byref(h)) == -1
     # matching without pointers
     assert L.pr_match_quantiles(None, None, None, 10, 1, 100, None, None, 64, None) == -1
+    # knots of matched ensembles: pointers, precision, sizes and the workspace
+    # are checked before any launch
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.pr_match_knots(None, p, 10, 1, 100, 64, p, 1 << 20, p, p, None) == -1
+    assert L.pr_match_knots(p, p, 10, 1, 100, 16, p, 1 << 20, p, p, None) == -1
+    assert L.pr_match_knots(p, p, 0, 1, 100, 64, p, 1 << 20, p, p, None) == -1
+    assert L.pr_match_knots(p, p, 10, 0, 100, 64, p, 1 << 20, p, p, None) == -1
+    assert L.pr_match_knots(p, p, 10, 1, 0, 64, p, 1 << 20, p, p, None) == -1
+    assert L.pr_match_knots(p, p, 1 << 20, 4, 100, 64, p, 1024, p, p, None) == -3
+    assert L.pr_parareal_knot_sorts(None) == -1
     # iterate on a NULL handle
     assert L.pr_parareal_iterate(None, 1, None, None, None) == -1
 
