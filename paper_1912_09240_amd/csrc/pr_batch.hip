@@ -241,14 +241,7 @@ __global__ void __launch_bounds__(256) match_batch_kernel(const MatchSeg *__rest
     for (int k = threadIdx.x; k < MB_TILE; k += blockDim.x) {
         const int64_t p = p0 + k;
         if (p >= M.n) break;
-        const double u = ((double)rank[M.base + p] + 0.5) / nd;
-        const double uq = u * Q;
-        double jf = floor(uq);
-        jf = jf < Q - 1.0 ? jf : Q - 1.0;
-        const int j = (int)jf;
-        const double w = uq - jf;
-        const double delta = (1.0 - w) * dk[j] + w * dk[j + 1];
-        x[M.base + p] = x[M.base + p] + delta;
+        x[M.base + p] = matched_value<double>(x[M.base + p], rank[M.base + p], dk, nd, Q);
     }
 }
 
@@ -325,6 +318,12 @@ struct Batch {
     int n_mtiles = 0;
     std::vector<int> mtile_first;  // per instance
     std::vector<int> mtile_count;
+    // knots of the new states from the fine results' sort (chunk and group
+    // extremes of every fine-result ensemble), a guarded sort where that fails
+    MkSeg *mk_seg = nullptr;
+    int *mk_gseg = nullptr;
+    int64_t mk_chunks = 0, mk_groups = 0;
+    int *flag = nullptr;
     int cur = 0, k = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -335,7 +334,7 @@ static void batch_free(Batch *b) {
     if (!b) return;
     void *ptrs[] = {b->inst, b->x[0], b->x[1], b->y[0], b->y[1], b->q, b->qn, b->qR, b->qf, b->qcs, b->rank,
                     b->ws, b->E, b->cu, b->chain, b->rho_a, b->units, b->counter, b->seg_f, b->tile_f, b->mseg,
-                    b->mtile};
+                    b->mtile, b->mk_seg, b->mk_gseg, b->flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &gx : b->graph)
@@ -512,7 +511,14 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
                            (const MatchSeg *)b->mseg, (const int *)b->mtile, 0, (const double *)b->qn,
                            (const double *)b->qf, Q, (const uint32_t *)b->rank, b->x[nx]);
         PR_LAUNCHED();
-        PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, Q, b->qR, nullptr, b->ws, st));
+        // knots of the new states: from the fine results' sort, the sort of
+        // the new states running only where the device flags a failure
+        const int mk = matched_knots_segments(b->ws, b->total_x, (int)b->seg_f_h.size(), b->mk_seg, b->mk_gseg,
+                                              b->mk_chunks, b->mk_groups, Q, b->qn, b->qf, b->qR, b->flag, st);
+        if (mk != PR_OK && mk != PR_E_UNSUPPORTED) return mk;
+        SortLayout LG = L;
+        if (mk == PR_OK) LG.guard = b->flag;
+        PR_CHECK(restrict_segments(b->x[nx], PR_F64, LG, b->total_x, b->tiles_f, Q, b->qR, nullptr, b->ws, st));
         hipLaunchKernelGGL(copy_f64, dim3(64), dim3(256), 0, st, (const double *)b->qn, b->q,
                            (int64_t)b->total_rows * (Q + 1));
         PR_LAUNCHED();
@@ -545,8 +551,16 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
                                (const MatchSeg *)b->mseg, (const int *)b->mtile, b->mtile_first[i],
                                (const double *)b->qn, (const double *)b->qf, Q, (const uint32_t *)b->rank, b->x[nx]);
             PR_LAUNCHED();
-            PR_CHECK(restrict_quantiles(b->x[nx] + xo + n, PR_F64, n, K, Q, nullptr, b->qR + (int64_t)(r0 + 1) * (Q + 1),
-                                        nullptr, nullptr, nullptr, nullptr, nullptr, b->ws, st));
+            double *qr = b->qR + (int64_t)(r0 + 1) * (Q + 1);
+            const int mk = matched_knots(b->ws, PR_F64, n, K, Q, b->qn + (int64_t)(r0 + 1) * (Q + 1), Q + 1,
+                                         b->qf + (int64_t)(r0 + 1) * (Q + 1), Q + 1, qr, b->flag, st);
+            if (mk == PR_OK)
+                PR_CHECK(restrict_knots_guarded(b->x[nx] + xo + n, PR_F64, n, K, Q, qr, b->ws, b->flag, st));
+            else if (mk == PR_E_UNSUPPORTED)
+                PR_CHECK(restrict_quantiles(b->x[nx] + xo + n, PR_F64, n, K, Q, nullptr, qr, nullptr, nullptr,
+                                            nullptr, nullptr, nullptr, b->ws, st));
+            else
+                return mk;
             hipLaunchKernelGGL(copy_f64, dim3(1), dim3(256), 0, st, (const double *)(b->qn + (int64_t)r0 * (Q + 1)),
                                b->q + (int64_t)r0 * (Q + 1), (int64_t)(K + 1) * (Q + 1));
             PR_LAUNCHED();
@@ -691,6 +705,20 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
     b->keys_f = keys;
     PR_CHECK(upload(b->seg_f, b->seg_f_h, st));
     PR_CHECK(upload(b->tile_f, tile_seg, st));
+    {
+        std::vector<MkSeg> mk;
+        std::vector<int> gseg;
+        for (const SortSeg &g : b->seg_f_h) {
+            const int64_t nch = (g.n + 63) / 64, ngr = (nch + 63) / 64;
+            mk.push_back(MkSeg{g.base, g.n, b->mk_chunks, b->mk_groups, g.qrow, g.qrow, g.qrow, 0});
+            for (int64_t t = 0; t < ngr; ++t) gseg.push_back((int)mk.size() - 1);
+            b->mk_chunks += nch;
+            b->mk_groups += ngr;
+        }
+        PR_CHECK(upload(b->mk_seg, mk, st));
+        PR_CHECK(upload(b->mk_gseg, gseg, st));
+        PB_ALLOC(b->flag, sizeof(int));
+    }
     // the sort arrays are indexed like the states (segment bases are state offsets)
     int64_t max_inst_keys = 0, max_inst_tiles = 0;
     int max_k = 1;

@@ -216,6 +216,20 @@ int match_strided(const MatchArgs &a, int64_t n, int k, int nq, int precision, h
 int matched_knots(const void *ws, int precision, int64_t n, int k, int nq, const double *qt, int64_t qt_stride,
                   const double *qp, int64_t qp_stride, double *q, int *flag, hipStream_t st);
 
+// The same for ensembles of unequal lengths (FP64) whose sort used a segment
+// table: segment s of the table holds ensemble s (its keys at base, n of
+// them), matched with knot rows qt_row, qp_row, its knots going to q_row;
+// ch0, gr0 number its first chunk (64 ranks) and group (4096 ranks) among
+// all segments' (host-computed prefix sums).  group_seg maps every group to
+// its segment.  Scratch: the key buffer of ws that the sort did not end in.
+struct MkSeg {
+    int64_t base, n, ch0, gr0;
+    int qt_row, qp_row, q_row, pad;
+};
+int matched_knots_segments(const void *ws, int64_t total_keys, int nseg, const MkSeg *segs, const int *group_seg,
+                           int64_t total_chunks, int64_t total_groups, int nq, const double *qt, const double *qp,
+                           double *q, int *flag, hipStream_t st);
+
 // x_in/y_in and x_out/y_out may alias (in place).
 int fine_propagate(const pr_sde *sde, const pr_schedule *sch, uint64_t seed, uint32_t inst, int64_t n,
                    int slice_first, int slice_count, const void *x_in, const void *y_in, void *x_out,
@@ -238,11 +252,17 @@ struct SortLayout {
     int nseg;
     const SortSeg *segs;   // unequal lengths: device table [nseg]
     const int *tile_seg;   // unequal lengths: device table [tiles]
+    const int *guard;      // device flag or NULL: while it reads 0 every kernel of the sort returns at once
 };
 int64_t sort_tiles(int64_t n);
 size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload);
 int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t total_keys, int64_t total_tiles,
                       int nq, double *q, uint32_t *rank, void *ws, hipStream_t st);
+// restrict_quantiles of k equal segments for knots only, every kernel
+// returning at once while *guard reads 0 (a sort that runs only where the
+// device decides it is needed, launched unconditionally).
+int restrict_knots_guarded(const void *x, int precision, int64_t n, int k, int nq, double *q, void *ws,
+                           const int *guard, hipStream_t st);
 size_t restrict_ws(int64_t n, int k, int precision);
 int restrict_quantiles(const void *x, int precision, int64_t n, int k, int nq, const pr_grid *hg, double *q,
                        uint32_t *rank, uint32_t *perm, double *xs, double *mom, uint32_t *hist, void *ws,

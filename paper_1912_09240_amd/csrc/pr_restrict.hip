@@ -133,6 +133,7 @@ rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__rest
     __shared__ uint32_t h[RS_WAVES][2][RS_RADIX];
     __shared__ double wsum[RS_WAVES][4];
     extern __shared__ uint32_t cell_h[];
+    if (L.guard && *L.guard == 0) return;
     const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < RS_WAVES * 2 * RS_RADIX; i += RS_THREADS) (&h[0][0][0])[i] = 0;
@@ -213,6 +214,7 @@ rs_count(const void *__restrict__ src, int shift, SortLayout L, uint32_t *__rest
 template <bool VAR>
 __global__ void __launch_bounds__(256) rs_rowscan(uint32_t *__restrict__ counts, uint32_t *__restrict__ totals,
                                                   SortLayout L) {
+    if (L.guard && *L.guard == 0) return;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= (int64_t)L.nseg * RS_RADIX) return;
     const int lane = threadIdx.x & 63;
@@ -253,6 +255,7 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
     __shared__ uint32_t wtot[RS_WAVES];
     __shared__ K stage[TILE];  // keys, then (reused) payload
 
+    if (L.guard && *L.guard == 0) return;
     const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
@@ -375,6 +378,7 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 template <typename K, bool VAR>
 __global__ void rs_knots(const K *__restrict__ sorted, SortLayout L, int nq, double *__restrict__ q) {
 #pragma clang fp contract(off)
+    if (L.guard && *L.guard == 0) return;
     int64_t base, n, tile0;
     int nblk, qrow;
     seg_ref<VAR>(L, blockIdx.x, base, n, tile0, nblk, qrow);
@@ -399,6 +403,7 @@ __global__ void rs_knots(const K *__restrict__ sorted, SortLayout L, int nq, dou
 
 template <bool VAR>
 __global__ void rs_moments(const double *__restrict__ part, SortLayout L, double *__restrict__ mom) {
+    if (L.guard && *L.guard == 0) return;
     int64_t base, n, tile0;
     int nblk, qrow;
     seg_ref<VAR>(L, blockIdx.x, base, n, tile0, nblk, qrow);
@@ -443,10 +448,59 @@ __device__ __forceinline__ K matched_key(K kp, int64_t r, const double *dk, doub
     return key_of(matched_value<V>((V)value_of(kp), (uint64_t)r, dk, nd, Q));
 }
 
-template <typename K>
-__device__ __forceinline__ void load_dk(double *dk, const double *qt, int64_t qts, const double *qp, int64_t qps,
-                                        int seg, int nq) {
-    for (int j = threadIdx.x; j <= nq; j += blockDim.x) dk[j] = qt[seg * qts + j] - qp[seg * qps + j];
+// Arguments of the matched-knot kernels.  Equal lengths (segs == NULL):
+// ensemble s holds keys [s n, s n + n) and knot rows s of qt, qp (strides
+// qts, qps) and q.  Unequal lengths: the segment table.
+struct MkArgs {
+    const void *sorted;  // the sorted keys
+    int64_t n, nch, ngr;  // equal lengths: ranks, chunks, groups per ensemble
+    const double *qt, *qp;
+    int64_t qts, qps;
+    double *q;
+    const MkSeg *segs;
+    const int *group_seg;
+    void *pre, *suf, *gx, *gn;  // extremes: [chunks], [chunks], [groups], [groups]
+    int nq;
+    int *flag;
+};
+
+// One ensemble as the kernels see it.
+struct MkRef {
+    int64_t base, n, nch, ngr, ch0, gr0;
+    const double *qt, *qp;
+    double *q;
+};
+
+template <bool VAR>
+__device__ __forceinline__ MkRef mk_ref(const MkArgs &A, int s) {
+    MkRef R;
+    if constexpr (VAR) {
+        const MkSeg g = A.segs[s];
+        R.base = g.base;
+        R.n = g.n;
+        R.nch = (g.n + 63) / 64;
+        R.ngr = (R.nch + 63) / 64;
+        R.ch0 = g.ch0;
+        R.gr0 = g.gr0;
+        R.qt = A.qt + (int64_t)g.qt_row * (A.nq + 1);
+        R.qp = A.qp + (int64_t)g.qp_row * (A.nq + 1);
+        R.q = A.q + (int64_t)g.q_row * (A.nq + 1);
+    } else {
+        R.base = s * A.n;
+        R.n = A.n;
+        R.nch = A.nch;
+        R.ngr = A.ngr;
+        R.ch0 = s * A.nch;
+        R.gr0 = s * A.ngr;
+        R.qt = A.qt + s * A.qts;
+        R.qp = A.qp + s * A.qps;
+        R.q = A.q + (int64_t)s * (A.nq + 1);
+    }
+    return R;
+}
+
+__device__ __forceinline__ void load_dk(double *dk, const MkRef &R, int nq) {
+    for (int j = threadIdx.x; j <= nq; j += blockDim.x) dk[j] = R.qt[j] - R.qp[j];
     __syncthreads();
 }
 
@@ -458,20 +512,25 @@ __device__ __forceinline__ void load_dk(double *dk, const double *qt, int64_t qt
 // from g on by mk_scan).
 constexpr int MK_GROUP = 64;
 
-template <typename K>
-__global__ void __launch_bounds__(256) mk_extremes(const K *__restrict__ sorted_all, int64_t n, int64_t nch,
-                                                   int64_t ngr, const double *__restrict__ qt, int64_t qts,
-                                                   const double *__restrict__ qp, int64_t qps, int nq,
-                                                   K *__restrict__ pre, K *__restrict__ suf, K *__restrict__ gx,
-                                                   K *__restrict__ gn) {
+template <typename K, bool VAR>
+__global__ void __launch_bounds__(256) mk_extremes(MkArgs A) {
     extern __shared__ double dk[];
     __shared__ K cx[MK_GROUP], cn[MK_GROUP];
-    const int seg = blockIdx.y;
-    load_dk<K>(dk, qt, qts, qp, qps, seg, nq);
-    const int64_t g = blockIdx.x;
+    int seg;
+    int64_t g;
+    if constexpr (VAR) {
+        seg = A.group_seg[blockIdx.x];
+        g = (int64_t)blockIdx.x - A.segs[seg].gr0;
+    } else {
+        seg = blockIdx.y;
+        g = blockIdx.x;
+    }
+    const MkRef R = mk_ref<VAR>(A, seg);
+    load_dk(dk, R, A.nq);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const K *sorted = sorted_all + seg * n;
-    const double nd = (double)n, Q = (double)nq;
+    const K *sorted = (const K *)A.sorted + R.base;
+    const int64_t n = R.n;
+    const double nd = (double)n, Q = (double)A.nq;
 #pragma unroll 1
     for (int i = 0; i < 4; ++i) {
         // ranks e0..e0+3 of chunk 16 w + 4 i + lane / 16 of the group
@@ -519,21 +578,23 @@ __global__ void __launch_bounds__(256) mk_extremes(const K *__restrict__ sorted_
         K ex = shfl_key(px, lane > 0 ? lane - 1 : 0);
         if (lane == 0) ex = 0;
         const int64_t c = g * MK_GROUP + lane;
-        if (c < nch) {
-            pre[seg * nch + c] = ex;
-            suf[seg * nch + c] = sn;
+        if (c < R.nch) {
+            ((K *)A.pre)[R.ch0 + c] = ex;
+            ((K *)A.suf)[R.ch0 + c] = sn;
         }
-        if (lane == 63) gx[seg * ngr + g] = px;
-        if (lane == 0) gn[seg * ngr + g] = sn;
+        if (lane == 63) ((K *)A.gx)[R.gr0 + g] = px;
+        if (lane == 0) ((K *)A.gn)[R.gr0 + g] = sn;
     }
 }
 
 // Per ensemble (one block of 256): gx[g] <- largest key of the groups before
 // g, gn[g] <- smallest key of the groups from g on.
-template <typename K>
-__global__ void __launch_bounds__(256) mk_scan(K *__restrict__ gx_all, K *__restrict__ gn_all, int64_t ngr) {
+template <typename K, bool VAR>
+__global__ void __launch_bounds__(256) mk_scan(MkArgs A) {
     __shared__ K wmx[4], wmn[4];
-    K *gx = gx_all + blockIdx.x * ngr, *gn = gn_all + blockIdx.x * ngr;
+    const MkRef R = mk_ref<VAR>(A, blockIdx.x);
+    const int64_t ngr = R.ngr;
+    K *gx = (K *)A.gx + R.gr0, *gn = (K *)A.gn + R.gr0;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t per = (ngr + 255) / 256;
     const int64_t g0 = tid * per < ngr ? tid * per : ngr, g1 = g0 + per < ngr ? g0 + per : ngr;
@@ -662,22 +723,21 @@ __device__ K order_stat(const K *sorted, int64_t n, const MkExt<K> &E, int64_t r
 
 // Midpoint (Hazen) knots of every matched ensemble, the arithmetic of
 // rs_knots on the order statistics: one wave per knot.
-template <typename K>
-__global__ void __launch_bounds__(256) mk_knots(const K *__restrict__ sorted_all, int64_t n, int64_t nch,
-                                                int64_t ngr, const double *__restrict__ qt, int64_t qts,
-                                                const double *__restrict__ qp, int64_t qps, int nq,
-                                                const K *__restrict__ pre, const K *__restrict__ suf,
-                                                const K *__restrict__ gx, const K *__restrict__ gn,
-                                                double *__restrict__ q, int *__restrict__ flag) {
+template <typename K, bool VAR>
+__global__ void __launch_bounds__(256) mk_knots(MkArgs A) {
 #pragma clang fp contract(off)
     extern __shared__ double dk[];
-    const int seg = blockIdx.y;
-    load_dk<K>(dk, qt, qts, qp, qps, seg, nq);
+    const MkRef R = mk_ref<VAR>(A, blockIdx.y);
+    load_dk(dk, R, A.nq);
+    const int nq = A.nq;
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j > nq) return;
     const int lane = threadIdx.x & 63;
-    const K *sorted = sorted_all + seg * n;
-    const MkExt<K> E{pre + seg * nch, suf + seg * nch, gx + seg * ngr, gn + seg * ngr, nch, ngr};
+    const int64_t n = R.n;
+    const K *sorted = (const K *)A.sorted + R.base;
+    const MkExt<K> E{(const K *)A.pre + R.ch0, (const K *)A.suf + R.ch0, (const K *)A.gx + R.gr0,
+                     (const K *)A.gn + R.gr0, R.nch, R.ngr};
+    int *flag = A.flag;
     const double nd = (double)n, Q = (double)nq;
     const double t = (double)((int64_t)j * n) / (double)nq - 0.5;
     double v;
@@ -693,7 +753,7 @@ __global__ void __launch_bounds__(256) mk_knots(const K *__restrict__ sorted_all
         v = a + f * (b - a);
         v = v < b ? v : b;
     }
-    if (lane == 0) q[(int64_t)seg * (nq + 1) + j] = v;
+    if (lane == 0) R.q[j] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -802,6 +862,17 @@ int restrict_quantiles(const void *x, int precision, int64_t n, int k, int nq, c
     return sort_impl<uint32_t, false>(x, L, n * k, tiles, nq, hg, q, rank, perm, xs, mom, hist, ws, st);
 }
 
+int restrict_knots_guarded(const void *x, int precision, int64_t n, int k, int nq, double *q, void *ws,
+                           const int *guard, hipStream_t st) {
+    SortLayout L{n, (int)sort_tiles(n), k, nullptr, nullptr, guard};
+    const int64_t tiles = (int64_t)L.nblk * k;
+    if (precision == PR_F64)
+        return sort_impl<uint64_t, false>(x, L, n * k, tiles, nq, nullptr, q, nullptr, nullptr, nullptr, nullptr,
+                                          nullptr, ws, st);
+    return sort_impl<uint32_t, false>(x, L, n * k, tiles, nq, nullptr, q, nullptr, nullptr, nullptr, nullptr,
+                                      nullptr, ws, st);
+}
+
 int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t total_keys, int64_t total_tiles,
                       int nq, double *q, uint32_t *rank, void *ws, hipStream_t st) {
     if (precision == PR_F64)
@@ -812,32 +883,58 @@ int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t
 }
 
 
+template <typename K, bool VAR>
+static int launch_matched_knots(const MkArgs &A, unsigned ngroups_or_x, int nseg, hipStream_t st) {
+    const size_t lds = (size_t)(A.nq + 1) * sizeof(double);
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)A.flag, (int64_t)1);
+    PR_LAUNCHED();
+    const dim3 eg = VAR ? dim3(ngroups_or_x) : dim3(ngroups_or_x, (unsigned)nseg);
+    hipLaunchKernelGGL((mk_extremes<K, VAR>), eg, dim3(256), lds, st, A);
+    PR_LAUNCHED();
+    hipLaunchKernelGGL((mk_scan<K, VAR>), dim3((unsigned)nseg), dim3(256), 0, st, A);
+    PR_LAUNCHED();
+    hipLaunchKernelGGL((mk_knots<K, VAR>), dim3((unsigned)((A.nq + 1 + 3) / 4), (unsigned)nseg), dim3(256), lds, st,
+                       A);
+    PR_LAUNCHED();
+    return PR_OK;
+}
+
+// The workspace as sort_impl lays it out: two key buffers of kb bytes, the
+// sorted keys in the one the last pass wrote; the other is free scratch.
+template <typename K>
+static void key_buffers(const void *ws, size_t kb, const void **sorted, void **scratch) {
+    char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    constexpr int last = (KeyTraits<K>::passes - 1) & 1;
+    *sorted = p + last * kb;
+    *scratch = p + (1 - last) * kb;
+}
+
 template <typename K>
 static int matched_knots_impl(const void *ws, int64_t n, int k, int nq, const double *qt, int64_t qts,
                               const double *qp, int64_t qps, double *q, int *flag, hipStream_t st) {
-    // the workspace as sort_impl lays it out: two key buffers, the sorted
-    // keys in the one the last pass wrote; the other is free scratch
-    char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     const size_t kb = align256((size_t)n * k * sizeof(K));
-    constexpr int last = (KeyTraits<K>::passes - 1) & 1;
-    const K *sorted = (const K *)(p + last * kb);
-    K *scratch = (K *)(p + (1 - last) * kb);
     const int64_t nch = (n + 63) / 64, ngr = (nch + MK_GROUP - 1) / MK_GROUP;
     if ((size_t)2 * (nch + ngr) * k * sizeof(K) > kb) return PR_E_UNSUPPORTED;
-    K *pre = scratch, *suf = pre + nch * k, *gx = suf + nch * k, *gn = gx + ngr * k;
-    const size_t lds = (size_t)(nq + 1) * sizeof(double);
-    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
-    PR_LAUNCHED();
-    hipLaunchKernelGGL(mk_extremes<K>, dim3((unsigned)ngr, (unsigned)k), dim3(256), lds, st, sorted, n, nch, ngr, qt,
-                       qts, qp, qps, nq, pre, suf, gx, gn);
-    PR_LAUNCHED();
-    hipLaunchKernelGGL(mk_scan<K>, dim3((unsigned)k), dim3(256), 0, st, gx, gn, ngr);
-    PR_LAUNCHED();
-    hipLaunchKernelGGL(mk_knots<K>, dim3((unsigned)((nq + 1 + 3) / 4), (unsigned)k), dim3(256), lds, st, sorted, n,
-                       nch, ngr, qt, qts, qp, qps, nq, (const K *)pre, (const K *)suf, (const K *)gx, (const K *)gn,
-                       q, flag);
-    PR_LAUNCHED();
-    return PR_OK;
+    const void *sorted;
+    void *scratch;
+    key_buffers<K>(ws, kb, &sorted, &scratch);
+    K *pre = (K *)scratch, *suf = pre + nch * k, *gx = suf + nch * k, *gn = gx + ngr * k;
+    const MkArgs A{sorted, n, nch, ngr, qt, qp, qts, qps, q, nullptr, nullptr, pre, suf, gx, gn, nq, flag};
+    return launch_matched_knots<K, false>(A, (unsigned)ngr, k, st);
+}
+
+int matched_knots_segments(const void *ws, int64_t total_keys, int nseg, const MkSeg *segs, const int *group_seg,
+                           int64_t total_chunks, int64_t total_groups, int nq, const double *qt, const double *qp,
+                           double *q, int *flag, hipStream_t st) {
+    const size_t kb = align256((size_t)total_keys * sizeof(uint64_t));
+    if ((size_t)2 * (total_chunks + total_groups) * sizeof(uint64_t) > kb) return PR_E_UNSUPPORTED;
+    const void *sorted;
+    void *scratch;
+    key_buffers<uint64_t>(ws, kb, &sorted, &scratch);
+    uint64_t *pre = (uint64_t *)scratch, *suf = pre + total_chunks, *gx = suf + total_chunks,
+             *gn = gx + total_groups;
+    const MkArgs A{sorted, 0, 0, 0, qt, qp, 0, 0, q, segs, group_seg, pre, suf, gx, gn, nq, flag};
+    return launch_matched_knots<uint64_t, true>(A, (unsigned)total_groups, nseg, st);
 }
 
 int matched_knots(const void *ws, int precision, int64_t n, int k, int nq, const double *qt, int64_t qt_stride,
