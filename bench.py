@@ -39,18 +39,19 @@ WORKLOAD = dict(lam=1.0, beta=2.0, eps=0.01, n=2 ** 20, dt=1e-4, T=10.0, K=64, c
 # loop control on the vector unit: Philox4x32-10 with the particle index as
 # the only lane-varying counter word (15 lane-varying 32x32->64 products and
 # 17 xor: 32), the Box-Muller pair from table lookups in LDS (u from bit
-# fields 2, -2 ln u 13, sqrt 7, sin/cos of the angle 14, two products 2: 38)
-# and the Euler-Maruyama update (10): 80, counted on isolated builds of each
-# part.  The figure is frozen so that the fraction moves only with speed.
-VALU_OPS_PER_STEP = 80
+# fields 2, -2 ln u from a 1024-cell table 12, sqrt 7, sin/cos of the angle
+# 14, two products 2: 37) and the Euler-Maruyama update (10): 79, counted on
+# isolated builds of each part.  The figure changes only with the method's
+# arithmetic, so that the fraction moves with speed alone.
+VALU_OPS_PER_STEP = 79
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
 
 # HBM bytes of one launch of the fine kernel (all 64 slices) from two
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
 # + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
-FINE_TRAFFIC_BYTES = (524366 * 2 + 1048576) * 1024
-FINE_SOURCES_SHA256 = "1df447b57830fa1fad191592ba5875a22f2ecc753e078a0daf1e173a0e96df8f"
+FINE_TRAFFIC_BYTES = (524410 * 2 + 1048576) * 1024
+FINE_SOURCES_SHA256 = "9b0537124177aba36e205c889e856c754b34fa72310dcda3d26284e61184a1c9"
 FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
                 "pr_noise_tables.inc"]
 

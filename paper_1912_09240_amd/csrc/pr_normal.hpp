@@ -11,13 +11,13 @@
 // 1 + k 2^-52 and 1 + f are doubles whose high word is 0x3FF00000 | (w >> 12)
 // and whose low word is a whole 32-bit word, so each costs one funnel shift.
 //
-// -2 ln u (table of 256 pairs, Tang-style reduction):
-//   u = m 2^e with m in [1/2, 1); c_i = 1/2 + (i + 1/2)/512 for the cell i
-//   of m (its top 8 mantissa bits), R_i = RN(1/c_i), g = m R_i - 1 with
-//   |g| <= 2^-9; -2 ln u = -2 e ln 2 + 2 ln R_i - 2 ln(1 + g), the last term
-//   as g (-2 + g - 2g^2/3 + g^3/2 - 2g^4/5 + g^5/3) (truncation below 2^-56
-//   relative).  The top cell uses R = 1 exactly, so g = m - 1 is exact and
-//   -2 ln u keeps full relative accuracy as u -> 1.
+// -2 ln u (table of 1024 pairs, Tang-style reduction):
+//   u = m 2^e with m in [1/2, 1); c_i = 1/2 + (i + 1/2)/2048 for the cell i
+//   of m (its top 10 mantissa bits), R_i = RN(1/c_i), g = m R_i - 1 with
+//   |g| <= 2^-11; -2 ln u = -2 e ln 2 + 2 ln R_i - 2 ln(1 + g), the last term
+//   as g (-2 + g - 2g^2/3 + g^3/2 - 2g^4/5) (the next term, g^6/3, is below
+//   2^-57 of 2|g|).  The top cell uses R = 1 exactly, so g = m - 1 is exact
+//   and -2 ln u keeps full relative accuracy as u -> 1.
 // sin and cos of pi t (table of 256 pairs):
 //   t = a_i + b/128 with a_i = (i + 1/2)/128 and b = (1 + f) - 3/2 exact in
 //   [-1/2, 1/2); with h = pi/128, sin(h b) to b^5 and cos(h b) - 1 to b^6
@@ -43,10 +43,10 @@ struct alignas(16) TabPair {
 };
 
 struct NoiseTab {
-    TabPair sc[256];  // sin(pi a_i), cos(pi a_i)
-    TabPair lg[256];  // R_i, 2 ln R_i
+    TabPair sc[256];   // sin(pi a_i), cos(pi a_i)
+    TabPair lg[1024];  // R_i, 2 ln R_i
 };
-constexpr int kNoiseTabDoubles = 1024;
+constexpr int kNoiseTabDoubles = 2560;
 
 static __constant__ double kNoiseTabDev[kNoiseTabDoubles] = {
 #define PR_NOISE_TABLE_ENTRIES
@@ -73,10 +73,9 @@ __host__ __device__ __forceinline__ double neg2_ln(double u, const TabPair *lg) 
     int e;
     const double m = mantissa_exponent(u, e);  // [1/2, 1)
     const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, m) >> 32);
-    const TabPair t = lg[(hi >> 12) & 255u];
+    const TabPair t = lg[(hi >> 10) & 1023u];
     const double g = __builtin_fma(m, t.a, -1.0);
-    double q = __builtin_fma(1.0 / 3.0, g, -0.4);
-    q = __builtin_fma(q, g, 0.5);
+    double q = __builtin_fma(-0.4, g, 0.5);
     q = __builtin_fma(q, g, -2.0 / 3.0);
     q = __builtin_fma(q, g, 1.0);
     q = __builtin_fma(q, g, -2.0);

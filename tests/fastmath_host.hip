@@ -11,7 +11,7 @@ static pr::NoiseTab host_tab() {
     };
     pr::NoiseTab t;
     for (int i = 0; i < 256; ++i) t.sc[i] = pr::TabPair{d[2 * i], d[2 * i + 1]};
-    for (int i = 0; i < 256; ++i) t.lg[i] = pr::TabPair{d[512 + 2 * i], d[512 + 2 * i + 1]};
+    for (int i = 0; i < 1024; ++i) t.lg[i] = pr::TabPair{d[512 + 2 * i], d[512 + 2 * i + 1]};
     return t;
 }
 

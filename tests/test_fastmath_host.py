@@ -55,8 +55,8 @@ def test_neg2_ln(fm):
         rng.integers(0, 2 ** 12, 10_000, dtype=np.int64),                # u near 2^-52
         np.array([0, 1, 2 ** 51 - 1, 2 ** 51, 2 ** 52 - 1], dtype=np.int64),
     ])
-    # cell boundaries of m in [1/2, 1): u = 1/2 + j/512 (+- one grid step)
-    kb = (np.arange(1, 256, dtype=np.int64) << 43) + (2 ** 51)
+    # cell boundaries of m in [1/2, 1): u = 1/2 + j/2048 (+- one grid step)
+    kb = (np.arange(1, 1024, dtype=np.int64) << 41) + (2 ** 51)
     k = np.concatenate([k, kb, kb - 1])
     u = _grid_u(k)
     out = np.empty_like(u)
