@@ -27,10 +27,18 @@ namespace pr {
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr int RS_RADIX = 256;
+constexpr int RS_ITEMS = 16;  // keys per thread and tile (tiles of RS_THREADS x RS_ITEMS keys)
 
 template <typename K> struct KeyTraits;
 template <> struct KeyTraits<uint64_t> { using V = double; static constexpr int passes = 8; };
 template <> struct KeyTraits<uint32_t> { using V = float;  static constexpr int passes = 4; };
+
+// Key buffer (0 or 1) of the workspace that holds the sorted keys when a
+// sort ends: 64-bit keys end in buffer 0 (the fix-up after the passes over
+// the high halves, or the complete sort arranged to end there), 32-bit keys
+// in the buffer the last of their 4 passes writes.
+template <typename K>
+constexpr int sorted_buffer() { return std::is_same<K, uint64_t>::value ? 0 : 1; }
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -370,6 +378,73 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fix-up after the passes over the high 32 bits of 64-bit keys.  The keys
+// are then ordered by their high halves, and among equal high halves by
+// particle (the passes are stable), so a run of equal high halves needs
+// only its own order by the full key, ties by position.  Every key finds the
+// run around it in the tile's keys (staged in LDS with FIX_MAX + 1 keys on
+// either side), counts the keys of the run that precede it in that order,
+// and goes to its final place with the rank, perm and sorted-value outputs
+// of the last pass.  A run longer than FIX_MAX sets *flag: the complete sort
+// then runs (guarded by the flag) and redoes every output.
+// ---------------------------------------------------------------------------
+constexpr int FIX_MAX = 64;
+constexpr int FIX_HALO = FIX_MAX + 1;
+
+template <bool VAR, bool PAYLOAD>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_fixup(const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in, uint64_t *__restrict__ keys_out,
+         SortLayout L, uint32_t *__restrict__ rank_out, uint32_t *__restrict__ perm_out, double *__restrict__ xs_out,
+         int *__restrict__ flag) {
+    constexpr int TILE = RS_THREADS * RS_ITEMS;
+    __shared__ uint64_t sk[TILE + 2 * FIX_HALO];
+    if (L.guard && *L.guard == 0) return;
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const uint64_t *k = keys_in + T.base;
+    const int64_t n = T.n, t0 = (int64_t)T.blk * TILE;
+    // sk[j] = k[t0 - FIX_HALO + j] where that position exists
+    for (int j = threadIdx.x; j < TILE + 2 * FIX_HALO; j += RS_THREADS) {
+        const int64_t q = t0 - FIX_HALO + j;
+        sk[j] = (q >= 0 && q < n) ? k[q] : 0ull;
+    }
+    __syncthreads();
+    bool too_long = false;
+#pragma unroll 4
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t p = t0 + (int64_t)i * RS_THREADS + threadIdx.x;
+        if (p >= n) break;
+        const int j = (int)(p - t0) + FIX_HALO;  // p in sk
+        const uint64_t kp = sk[j];
+        const uint32_t hp = (uint32_t)(kp >> 32);
+        // the run [p - back, p + fwd] of equal high halves, at most FIX_MAX long
+        int back = 0, fwd = 0;
+        while (back < FIX_MAX && p - back > 0 && (uint32_t)(sk[j - back - 1] >> 32) == hp) ++back;
+        while (fwd < FIX_MAX && p + fwd + 1 < n && (uint32_t)(sk[j + fwd + 1] >> 32) == hp) ++fwd;
+        int64_t pos = p;
+        if (back + fwd + 1 > FIX_MAX) {
+            too_long = true;
+            continue;
+        }
+        if (back + fwd > 0) {
+            int r = 0;
+            for (int b = -back; b <= fwd; ++b) {
+                const uint64_t kb = sk[j + b];
+                r += (kb < kp || (kb == kp && b < 0)) ? 1 : 0;
+            }
+            pos = p - back + r;
+        }
+        keys_out[T.base + pos] = kp;
+        if constexpr (PAYLOAD) {
+            const uint32_t v = vals_in[T.base + p];
+            if (rank_out && (int64_t)v < n) rank_out[T.base + v] = (uint32_t)pos;
+            if (perm_out) perm_out[T.base + pos] = v;
+        }
+        if (xs_out) xs_out[T.base + pos] = value_of(kp);
+    }
+    if (too_long) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -761,8 +836,6 @@ __global__ void __launch_bounds__(256) mk_knots(MkArgs A) {
 // ---------------------------------------------------------------------------
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-constexpr int RS_ITEMS = 16;
-
 int64_t sort_tiles(int64_t n) {
     const int64_t tile = (int64_t)RS_THREADS * RS_ITEMS;
     return (n + tile - 1) / tile;
@@ -771,7 +844,7 @@ int64_t sort_tiles(int64_t n) {
 size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload) {
     const size_t ks = precision == PR_F32 ? 4 : 8;
     size_t b = align256(total_keys * ks) * 2 + align256((size_t)total_tiles * RS_RADIX * 4) +
-               align256((size_t)nseg * RS_RADIX * 4) + align256((size_t)total_tiles * 4 * 8) + 256;
+               align256((size_t)nseg * RS_RADIX * 4) + align256((size_t)total_tiles * 4 * 8) + 256 + 256;
     if (payload) b += align256(total_keys * 4) * 2;
     return b;
 }
@@ -810,39 +883,63 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
         hipLaunchKernelGGL(zero_u32, dim3((unsigned)blocks), dim3(256), 0, st, hist, cnt);
         PR_LAUNCHED();
     }
-    constexpr int P = KeyTraits<K>::passes;
+    int *flag = (int *)p;  // 256 bytes after the payload (or the moment) buffers
+    if (payload) flag = (int *)((char *)vals[1] + align256(total_keys * 4));
     const dim3 grid((unsigned)total_tiles);
     const dim3 rows((unsigned)(((int64_t)L.nseg * RS_RADIX + 3) / 4));
-    for (int pass = 0; pass < P; ++pass) {
-        const int shift = 8 * pass;
-        const int in = (pass + 1) & 1, out = pass & 1;  // pass 0 writes buffer 0
-        if (pass == 0)
-            hipLaunchKernelGGL((rs_count<K, ITEMS, true, VAR>), grid, dim3(RS_THREADS), cell_lds, st, x, shift, L,
-                               counts, mom ? mom_part : nullptr, ha);
+    // One LSD pass over the byte at shift: keys[in] -> keys[out] (pass 0
+    // reads the values), with the statistics on the first read and the rank,
+    // perm and sorted-value outputs on the last pass.
+    auto pass = [&](const SortLayout &LL, int shift, bool first, bool last, int in, int out, bool stats) -> int {
+        if (first)
+            hipLaunchKernelGGL((rs_count<K, ITEMS, true, VAR>), grid, dim3(RS_THREADS), stats ? cell_lds : 0, st, x,
+                               shift, LL, counts, (stats && mom) ? mom_part : nullptr,
+                               stats ? ha : HistArgs{nullptr, 0, 0.0, 0.0});
         else
             hipLaunchKernelGGL((rs_count<K, ITEMS, false, VAR>), grid, dim3(RS_THREADS), 0, st,
-                               (const void *)keys[in], shift, L, counts, nullptr, HistArgs{nullptr, 0, 0.0, 0.0});
+                               (const void *)keys[in], shift, LL, counts, nullptr, HistArgs{nullptr, 0, 0.0, 0.0});
         PR_LAUNCHED();
-        hipLaunchKernelGGL((rs_rowscan<VAR>), rows, dim3(256), 0, st, counts, totals, L);
+        hipLaunchKernelGGL((rs_rowscan<VAR>), rows, dim3(256), 0, st, counts, totals, LL);
         PR_LAUNCHED();
-        const bool last = pass == P - 1;
 #define PR_SCATTER(FIRST, LAST, PAY, SRC, VIN, VOUT)                                                            \
     hipLaunchKernelGGL((rs_scatter<K, ITEMS, FIRST, LAST, PAY, VAR>), grid, dim3(RS_THREADS), 0, st, SRC, VIN,     \
-                       keys[out], VOUT, (const uint32_t *)counts, (const uint32_t *)totals, shift, L,          \
+                       keys[out], VOUT, (const uint32_t *)counts, (const uint32_t *)totals, shift, LL,         \
                        LAST ? rank : nullptr, LAST ? perm : nullptr, LAST ? xs : nullptr)
         if (payload) {
-            if (pass == 0) PR_SCATTER(true, false, true, x, nullptr, vals[out]);
+            if (first) PR_SCATTER(true, false, true, x, nullptr, vals[out]);
             else if (!last) PR_SCATTER(false, false, true, (const void *)keys[in], vals[in], vals[out]);
             else PR_SCATTER(false, true, true, (const void *)keys[in], vals[in], nullptr);
         } else {
-            if (pass == 0) PR_SCATTER(true, false, false, x, nullptr, nullptr);
+            if (first) PR_SCATTER(true, false, false, x, nullptr, nullptr);
             else if (!last) PR_SCATTER(false, false, false, (const void *)keys[in], nullptr, nullptr);
             else PR_SCATTER(false, true, false, (const void *)keys[in], nullptr, nullptr);
         }
 #undef PR_SCATTER
         PR_LAUNCHED();
+        return PR_OK;
+    };
+    constexpr int P = KeyTraits<K>::passes;
+    if constexpr (std::is_same<K, uint64_t>::value) {
+        // the high 32 bits (passes 4..7, ending in buffer 1), the fix-up of
+        // runs of equal high halves into buffer 0, and the complete sort
+        // (also ending in buffer 0) only where a run is too long for it
+        for (int j = 0; j < 4; ++j) PR_CHECK(pass(L, 32 + 8 * j, j == 0, false, (j + 1) & 1, j & 1, true));
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
+        PR_LAUNCHED();
+        if (payload)
+            hipLaunchKernelGGL((rs_fixup<VAR, true>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
+                               (const uint32_t *)vals[1], (uint64_t *)keys[0], L, rank, perm, xs, flag);
+        else
+            hipLaunchKernelGGL((rs_fixup<VAR, false>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
+                               (const uint32_t *)nullptr, (uint64_t *)keys[0], L, rank, perm, xs, flag);
+        PR_LAUNCHED();
+        SortLayout LG = L;
+        LG.guard = flag;
+        for (int j = 0; j < P; ++j) PR_CHECK(pass(LG, 8 * j, j == 0, j == P - 1, j & 1, (j + 1) & 1, false));
+    } else {
+        for (int j = 0; j < P; ++j) PR_CHECK(pass(L, 8 * j, j == 0, j == P - 1, (j + 1) & 1, j & 1, true));
     }
-    const K *sorted = keys[(P - 1) & 1];
+    const K *sorted = keys[sorted_buffer<K>()];
     hipLaunchKernelGGL((rs_knots<K, VAR>), dim3(L.nseg), dim3(128), 0, st, sorted, L, nq, q);
     PR_LAUNCHED();
     if (mom) {
@@ -904,7 +1001,7 @@ static int launch_matched_knots(const MkArgs &A, unsigned ngroups_or_x, int nseg
 template <typename K>
 static void key_buffers(const void *ws, size_t kb, const void **sorted, void **scratch) {
     char *p = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-    constexpr int last = (KeyTraits<K>::passes - 1) & 1;
+    constexpr int last = sorted_buffer<K>();
     *sorted = p + last * kb;
     *scratch = p + (1 - last) * kb;
 }
