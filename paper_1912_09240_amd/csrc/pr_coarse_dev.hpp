@@ -115,6 +115,14 @@ __device__ inline void masses_to_knots_block(const double *rho, double *C, const
     }
 }
 
+// The value of v in lane l (uniform l) of the wave.
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Whether the rounded mean a/ca exceeds the rounded mean b/cb (counts >= 1).
 // Where the cross products a*cb and b*ca differ by more than 2^-49 of their
 // magnitudes (plus 2^-1000), the exact means differ by more than 2^-50 of
@@ -150,10 +158,22 @@ __host__ __device__ inline bool mean_above(double a, int ca, double b, int cb) {
 // every merge that reaches lo): the values the serial pass over a longer
 // input would compare with the mean of the last pool before the stretch.
 // *lm receives the mean of the pool holding hi - 1.
+//
+// WAVE: called by a whole wave with the same arguments (every lane runs the
+// same scalar steps on the same values).  Where T holds more than one value
+// and the next value merges into it while B stays below, the wave takes the
+// run ahead at once: lane j adds v[i + j] to T's sum after the lanes before
+// it, in the serial order, and checks the two comparisons the serial pass
+// would make for that value; the longest prefix of lanes that pass is
+// committed (windows of 8 values, doubling up to 64 while whole windows
+// pass).  A decreasing run of L values then costs about L / 64 windows
+// instead of L serial steps.
+template <bool WAVE = false>
 __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi, const int *vio, int nv,
                                                  double *S, int *SC, double *fm, double *lm) {
 #pragma clang fp contract(off)
     int nb = 0, vi = 0;
+    int win = 8;
     double fmin_ = v[lo];
     int i = vio[0];
     double tS = v[i], bS = 0.0;
@@ -163,15 +183,30 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
     double vcur = v[i < hi ? i : hi - 1];
     while (i < hi) {
         if (tC == 1) {
-            // first violation at or after i - 1 (binary search: a decreasing
-            // run leaves a long stretch of consumed ones behind)
-            int lo2 = vi, hi2 = nv;
-            while (lo2 < hi2) {
-                const int mid = (lo2 + hi2) >> 1;
-                if (vio[mid] < i - 1) lo2 = mid + 1;
-                else hi2 = mid;
+            // first violation at or after i - 1 (a decreasing run leaves a
+            // long stretch of consumed ones behind)
+            if constexpr (WAVE) {
+                // 64 entries per look, one per lane
+                const int lane = (int)(threadIdx.x & 63);
+                while (true) {
+                    const int idx = vi + lane;
+                    const uint64_t bm = __ballot(idx >= nv || vio[idx] >= i - 1);
+                    if (bm) {
+                        vi += __builtin_ctzll(bm);
+                        break;
+                    }
+                    vi += 64;
+                }
+                if (vi > nv) vi = nv;
+            } else {
+                int lo2 = vi, hi2 = nv;  // binary search
+                while (lo2 < hi2) {
+                    const int mid = (lo2 + hi2) >> 1;
+                    if (vio[mid] < i - 1) lo2 = mid + 1;
+                    else hi2 = mid;
+                }
+                vi = lo2;
             }
-            vi = lo2;
             if (vi == nv) break;  // non-decreasing from v[i-1] on
             const int jn = vio[vi];
             if (jn > i - 1) {
@@ -183,6 +218,41 @@ __host__ __device__ inline int pava_sparse_range(const double *v, int lo, int hi
                 i = jn + 1;
                 vcur = v[i];
             }
+        }
+        if constexpr (WAVE) {
+            if (tC > 1 && mean_above(tS, tC, vcur, 1) && (tSt == lo || !mean_above(bS, bC, vcur + tS, tC + 1))) {
+                const int lane = (int)(threadIdx.x & 63);
+                const int m = hi - i < win ? hi - i : win;
+                const double ve = lane < m ? v[i + lane] : 0.0;  // one load for the window
+                double acc = tS, prev = tS;  // T's sum before and after this lane's value
+                for (int k = 0; k < m; ++k) {
+                    const double vk = lane_value(ve, k);
+                    if (k <= lane) {
+                        prev = acc;
+                        acc = vk + acc;
+                    }
+                }
+                const int cb = tC + lane;
+                const bool ok = lane < m && mean_above(prev, cb, ve, 1) &&
+                                (tSt == lo || !mean_above(bS, bC, acc, cb + 1));
+                const uint64_t bad = __ballot(!ok);
+                const int f = bad ? __builtin_ctzll(bad) : 64;  // >= 1: lane 0 passes
+                if (tSt == lo) {
+                    double mm = lane < f ? acc / (double)(cb + 1) : INFINITY;
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const double o = __shfl_xor(mm, off);
+                        mm = o < mm ? o : mm;
+                    }
+                    if (mm < fmin_) fmin_ = mm;
+                }
+                tS = lane_value(acc, f - 1);
+                tC += f;
+                i += f;
+                win = f == m ? (win < 64 ? 2 * win : 64) : 8;
+                vcur = v[i < hi ? i : hi - 1];
+                continue;
+            }
+            win = 8;
         }
         double s = vcur;
         vcur = v[i + 1 < hi ? i + 1 : i];  // the next value, loaded ahead
@@ -257,7 +327,7 @@ __host__ __device__ inline void pava_sparse(const double *v, int L, const int *v
 // violations vio[0..nv) (increasing), with the arithmetic of the serial
 // stack form.  The input is cut where every value before is below every
 // value after (no pool can reach across such a cut); the stretches between
-// cuts that hold violations run pava_sparse_range, one thread each.  Where
+// cuts that hold violations run pava_sparse_range, one wave each.  Where
 // the last pool of a stretch has a mean above a value the first pool of the
 // next one takes (rounding can put a pool's mean above its largest value),
 // the serial pass would have merged across the cut: those cuts are dropped
@@ -377,9 +447,16 @@ __device__ inline void pava_block_chunked(double *v, int L, const int *vio, int 
     }
     while (true) {
         const int nc = pc.nc;
-        for (int k = tid; k < nc; k += nt)
-            pc.np[k] = pava_sparse_range(v, pc.cb[k], pc.cb[k + 1], vio + pc.fv[k], pc.fv[k + 1] - pc.fv[k], S, SC,
-                                         &pc.fm[k], &pc.lm[k]);
+        for (int k = w; k < nc; k += nt / 64) {  // one wave per stretch
+            double fm, lm;
+            const int np = pava_sparse_range<true>(v, pc.cb[k], pc.cb[k + 1], vio + pc.fv[k],
+                                                   pc.fv[k + 1] - pc.fv[k], S, SC, &fm, &lm);
+            if (lane == 0) {
+                pc.np[k] = np;
+                pc.fm[k] = fm;
+                pc.lm[k] = lm;
+            }
+        }
         __syncthreads();
         // keep cut k (1 <= k < nc) unless the serial pass would cross it
         const int per = (nc + nt - 1) / nt;
@@ -491,7 +568,11 @@ __device__ inline void pava_block(double *v, int L, double *S, int *SC, int *vio
     if ((int)threadIdx.x == nt - 1) nbad = base;
     __syncthreads();
     if (nbad == 0) return;
-    if (threadIdx.x == 0) pava_sparse(v, L, vio, nbad, S, SC, &npools);
+    if (w == 0) {  // the whole first wave runs the pass
+        double fm, lm;
+        const int np = pava_sparse_range<true>(v, 0, L, vio, nbad, S, SC, &fm, &lm);
+        if (lane == 0) npools = np;
+    }
     __syncthreads();
     const int wl = min(64, nt - 64 * w);  // lanes of this wave
     for (int q = w; q < npools; q += (nt + 63) / 64) {  // one wave per pool

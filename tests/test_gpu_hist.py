@@ -78,6 +78,35 @@ def _hists(rng, k, I, gaps):
     return r / r.sum(axis=1, keepdims=True)
 
 
+def test_jump_quantile_long_decreasing_runs(torch_dev):
+    """Fine histograms with all their mass in three cells (flat fine quantile
+    functions) against smooth coarse ones that disagree: the reconstructed
+    quantile function then decreases over long stretches of levels, the case
+    whose monotone repair merges hundreds of values into one pool."""
+    torch = torch_dev
+    I, k = 1024, 4
+    _say(f"hist jump quantile long runs I={I}")
+    g, og = _grids(I)
+    c = og.mids
+
+    def gauss(mu, sd):
+        r = np.exp(-0.5 * ((c - mu) / sd) ** 2)
+        return r / r.sum()
+
+    rc = np.stack([gauss(0.0, 1.0), gauss(0.5, 0.7), gauss(-1.0, 1.2), gauss(0.2, 0.5)])
+    rcs = np.stack([gauss(0.3, 0.8), gauss(-0.2, 1.1), gauss(-0.5, 0.6), gauss(0.0, 0.9)])
+    rf = np.zeros((k, I))
+    for s, cells in enumerate([(300, 512, 700), (100, 101, 900), (512, 513, 514), (10, 600, 1000)]):
+        rf[s, list(cells)] = [0.3, 0.4, 0.3]
+    out = torch.empty((k, I), dtype=torch.float64, device="cuda")
+    ws = torch.empty(pr.pr_hist_jump_workspace_size(k, I), dtype=torch.uint8, device="cuda")
+    pr.pr_hist_jump(pr.PR_J_QUANTILE, _dev(torch, rc), _dev(torch, rf), _dev(torch, rcs), k, g, out, ws)
+    got = out.cpu().numpy()
+    for s in range(k):
+        ref = H.jump(pr.PR_J_QUANTILE, rc[s], rf[s], rcs[s], og)
+        assert np.array_equal(got[s], ref), (s, np.abs(got[s] - ref).max())
+
+
 @pytest.mark.parametrize("kind", [pr.PR_J_ADD, pr.PR_J_MULT, pr.PR_J_ROT, pr.PR_J_QUANTILE])
 @pytest.mark.parametrize("I,gaps", [(50, False), (200, True), (1024, True)])
 def test_jump_bitwise(torch_dev, kind, I, gaps):
