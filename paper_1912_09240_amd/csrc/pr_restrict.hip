@@ -412,37 +412,56 @@ rs_fixup(const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ vals
     }
     __syncthreads();
     bool too_long = false;
-#pragma unroll 4
+    // final places first, then all stores of the tile's keys at once
+    int64_t pos[RS_ITEMS];
+    uint64_t key[RS_ITEMS];
+#pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
         const int64_t p = t0 + (int64_t)i * RS_THREADS + threadIdx.x;
-        if (p >= n) break;
-        const int j = (int)(p - t0) + FIX_HALO;  // p in sk
-        const uint64_t kp = sk[j];
-        const uint32_t hp = (uint32_t)(kp >> 32);
-        // the run [p - back, p + fwd] of equal high halves, at most FIX_MAX long
-        int back = 0, fwd = 0;
-        while (back < FIX_MAX && p - back > 0 && (uint32_t)(sk[j - back - 1] >> 32) == hp) ++back;
-        while (fwd < FIX_MAX && p + fwd + 1 < n && (uint32_t)(sk[j + fwd + 1] >> 32) == hp) ++fwd;
-        int64_t pos = p;
-        if (back + fwd + 1 > FIX_MAX) {
-            too_long = true;
-            continue;
-        }
-        if (back + fwd > 0) {
-            int r = 0;
-            for (int b = -back; b <= fwd; ++b) {
-                const uint64_t kb = sk[j + b];
-                r += (kb < kp || (kb == kp && b < 0)) ? 1 : 0;
+        pos[i] = -1;
+        key[i] = 0;
+        if (p < n) {
+            const int j = (int)(p - t0) + FIX_HALO;  // p in sk
+            const uint64_t kp = sk[j];
+            const uint32_t hp = (uint32_t)(kp >> 32);
+            // the run [p - back, p + fwd] of equal high halves, at most FIX_MAX long
+            int back = 0, fwd = 0;
+            while (back < FIX_MAX && p - back > 0 && (uint32_t)(sk[j - back - 1] >> 32) == hp) ++back;
+            while (fwd < FIX_MAX && p + fwd + 1 < n && (uint32_t)(sk[j + fwd + 1] >> 32) == hp) ++fwd;
+            key[i] = kp;
+            if (back + fwd + 1 > FIX_MAX) {
+                too_long = true;
+            } else if (back + fwd == 0) {
+                pos[i] = p;
+            } else {
+                int r = 0;
+                for (int b = -back; b <= fwd; ++b) {
+                    const uint64_t kb = sk[j + b];
+                    r += (kb < kp || (kb == kp && b < 0)) ? 1 : 0;
+                }
+                pos[i] = p - back + r;
             }
-            pos = p - back + r;
         }
-        keys_out[T.base + pos] = kp;
-        if constexpr (PAYLOAD) {
-            const uint32_t v = vals_in[T.base + p];
-            if (rank_out && (int64_t)v < n) rank_out[T.base + v] = (uint32_t)pos;
-            if (perm_out) perm_out[T.base + pos] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        if (pos[i] >= 0) {
+            keys_out[T.base + pos[i]] = key[i];
+            if (xs_out) xs_out[T.base + pos[i]] = value_of(key[i]);
         }
-        if (xs_out) xs_out[T.base + pos] = value_of(kp);
+    }
+    if constexpr (PAYLOAD) {
+        uint32_t val[RS_ITEMS];
+#pragma unroll
+        for (int i = 0; i < RS_ITEMS; ++i)
+            val[i] = pos[i] >= 0 ? vals_in[T.base + t0 + (int64_t)i * RS_THREADS + threadIdx.x] : 0u;
+#pragma unroll
+        for (int i = 0; i < RS_ITEMS; ++i) {
+            if (pos[i] >= 0) {
+                if (rank_out && (int64_t)val[i] < n) rank_out[T.base + val[i]] = (uint32_t)pos[i];
+                if (perm_out) perm_out[T.base + pos[i]] = val[i];
+            }
+        }
     }
     if (too_long) *flag = 1;
 }

@@ -3,7 +3,8 @@ that rocprofv3 counter passes cover a handful of dispatches.
 
     python -m paper_1912_09240_amd.profile_workload fine      # all 64 slices, one launch
     python -m paper_1912_09240_amd.profile_workload restrict  # sort of 64 x 2^20 keys with ranks
-    python -m paper_1912_09240_amd.profile_workload match     # matching of 64 x 2^20 particles
+    python -m paper_1912_09240_amd.profile_workload match     # matching of 64 x 2^20 particles and the
+                                                              # knots of the matched states
     python -m paper_1912_09240_amd.profile_workload copy      # device-to-device copy of 1 GiB
     python -m paper_1912_09240_amd.profile_workload hist      # histograms, marginal matching and
                                                               # stratified resampling, 64 x 2^20
@@ -56,8 +57,11 @@ def match():
     rank = torch.empty((K, N), dtype=torch.int32, device="cuda")
     pr.pr_restrict_quantiles(x, pr.PR_F64, N, K, NQ, q, ws, rank=rank)
     qt = q + 0.01
+    qm = torch.empty_like(q)
+    flag = torch.zeros((1,), dtype=torch.int32, device="cuda")
     for _ in range(2):
         pr.pr_match_quantiles(qt, q, rank, N, K, NQ, x, x)
+        pr.pr_match_knots(qt, q, N, K, NQ, ws, qm, flag)
         torch.cuda.synchronize()
 
 
