@@ -161,3 +161,29 @@ def test_parareal_takes_knots_without_sort(torch_dev):
         assert pr.pr_parareal_knot_sorts(h) == 0
     finally:
         pr.pr_parareal_destroy(h)
+
+
+def test_parareal_sorts_new_states_when_needed(torch_dev):
+    """With three particles in each of 32 slices the workspace has no room
+    for the chunk extremes: every iteration then takes the new knots by a
+    sort of the new states, and they still equal the sort of the states."""
+    torch = torch_dev
+    _say("parareal knots by sort")
+    n, K, nq = 3, 32, 10
+    h = pr.pr_parareal_create(pr.Sde(lam=1.0, eps=0.1, beta=2.0), pr.Schedule(320, K, 1e-3),
+                              pr.Grid(n_cells=50, n_q=nq), 0, 0, n, 0)
+    try:
+        ws = torch.empty(pr.pr_restrict_workspace_size(n, 1), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            pr.pr_parareal_iterate(h, 1)
+        for t in range(K + 1):
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+            q = torch.empty(nq + 1, dtype=torch.float64, device="cuda")
+            qs = torch.empty(nq + 1, dtype=torch.float64, device="cuda")
+            pr.pr_parareal_state(h, t, x=x, q=q)
+            pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, nq, qs, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(q, qs), t
+        assert pr.pr_parareal_knot_sorts(h) == 2
+    finally:
+        pr.pr_parareal_destroy(h)
