@@ -246,6 +246,27 @@ __global__ void __launch_bounds__(256) rs_rowscan(uint32_t *__restrict__ counts,
     if (lane == 0) totals[(int64_t)s * RS_RADIX + d] = carry;
 }
 
+// Row scan for many short segments (the segment-table layout): one block per
+// segment, one thread per digit walking that digit's tile counts, so that a
+// launch has one block per segment instead of one wave per (segment, digit).
+template <bool VAR>
+__global__ void __launch_bounds__(256) rs_rowscan_seg(uint32_t *__restrict__ counts, uint32_t *__restrict__ totals,
+                                                      SortLayout L) {
+    if (L.guard && *L.guard == 0) return;
+    const int s = blockIdx.x, d = threadIdx.x;  // RS_RADIX threads
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, s, base, n, tile0, nblk, qrow);
+    uint32_t *c = counts + tile0 * RS_RADIX + (int64_t)d * nblk;
+    uint32_t carry = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const uint32_t v = c[b];
+        c[b] = carry;
+        carry += v;
+    }
+    totals[(int64_t)s * RS_RADIX + d] = carry;
+}
+
 // ---------------------------------------------------------------------------
 // Scatter.
 // ---------------------------------------------------------------------------
@@ -918,7 +939,11 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
             hipLaunchKernelGGL((rs_count<K, ITEMS, false, VAR>), grid, dim3(RS_THREADS), 0, st,
                                (const void *)keys[in], shift, LL, counts, nullptr, HistArgs{nullptr, 0, 0.0, 0.0});
         PR_LAUNCHED();
-        hipLaunchKernelGGL((rs_rowscan<VAR>), rows, dim3(256), 0, st, counts, totals, LL);
+        if constexpr (VAR)
+            hipLaunchKernelGGL((rs_rowscan_seg<VAR>), dim3((unsigned)LL.nseg), dim3(RS_RADIX), 0, st, counts, totals,
+                               LL);
+        else
+            hipLaunchKernelGGL((rs_rowscan<VAR>), rows, dim3(256), 0, st, counts, totals, LL);
         PR_LAUNCHED();
 #define PR_SCATTER(FIRST, LAST, PAY, SRC, VIN, VOUT)                                                            \
     hipLaunchKernelGGL((rs_scatter<K, ITEMS, FIRST, LAST, PAY, VAR>), grid, dim3(RS_THREADS), 0, st, SRC, VIN,     \
