@@ -46,6 +46,7 @@ WORKLOAD = dict(lam=1.0, beta=2.0, eps=0.01, n=2 ** 20, dt=1e-4, T=10.0, K=64, c
 VALU_OPS_PER_STEP = 79
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12  # B/s
 
 # HBM bytes of one launch of the fine kernel (all 64 slices) from two
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
@@ -501,6 +502,16 @@ def main():
                     fine_ms=phases["fine"], fine_particle_steps_per_s=fine_rate,
                     ops_per_particle_step=VALU_OPS_PER_STEP)
 
+    # the whole iteration against its floor: the fine steps at the VALU issue
+    # peak plus the algorithmic bytes of restriction (8 B key read + 4 B rank
+    # write), matching (20 B) and the knots of the new states (8 B sorted key
+    # read) per particle and slice at 8 TB/s; the serial chain and the coarse
+    # step are latency and count as overhead
+    floor_s = VALU_OPS_PER_STEP * n * S / VALU_PEAK + n * K * (12 + 20 + 8) / HBM_PEAK
+    sweep_roofline = dict(floor_ms=1e3 * floor_s, measured_ms=ms_step, frac=1e3 * floor_s / ms_step,
+                          basis=f"{VALU_OPS_PER_STEP} VALU instructions per particle-step at "
+                                f"{VALU_PEAK / 1e12:.1f} T lane-instructions/s, 40 B per particle and slice at 8 TB/s")
+
     out = dict(metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
@@ -509,6 +520,7 @@ def main():
                                     "one parareal iteration per step", particles=n, fine_steps=S, slices=K,
                            cells=w["cells"], quantile_levels=nq, flags=args.flags, seed=w["seed"]),
                roofline=roofline,
+               sweep_roofline=sweep_roofline,
                phases_ms=phases,
                quantile_error=dict(at_T=[float(errs[2 * i]) for i in range(args.warmup + args.steps)],
                                    max_over_slices=[float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]),
