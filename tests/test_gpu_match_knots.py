@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 
 import paper_1912_09240_amd as pr
+from oracle import iterate as OI
+from oracle import restrict as OR
 from tests import inputs
 
 pytestmark = pytest.mark.gpu
@@ -76,6 +78,42 @@ def test_match_knots_equal_sorted_knots(torch_dev, k, n, ties):
         assert fl == 0
     if fl == 0:
         assert np.array_equal(qf.view(np.uint64), qs.view(np.uint64))
+
+
+@pytest.mark.parametrize("k,n", [(3, 5_000), (2, 70_001)])
+def test_match_knots_against_the_oracle(torch_dev, k, n):
+    """The knots without a sort against the oracle's own chain: its
+    restriction of the priors, its matching to the moved knots, its sort and
+    Hazen knots of the matched ensembles -- bit for bit."""
+    torch = torch_dev
+    _say(f"match knots vs oracle k={k} n={n}")
+    nq = 100
+    xs = inputs.slow_values(900 + n, k, n, ties=False)
+    lev = np.arange(nq + 1) / nq
+    shift = 0.01 + 0.02 * np.sin(3.0 * np.pi * lev)
+    qp_o, qt_o, qref = [], [], []
+    for s in range(k):
+        _, rank, srt = OR.sort_ranks(xs[s])
+        qp = OR.hazen_knots(srt, nq)
+        qt = qp + shift
+        xm = OI.match_quantiles(xs[s], rank, qt, qp)
+        qp_o.append(qp)
+        qt_o.append(qt)
+        qref.append(OR.hazen_knots(OR.sort_ranks(xm)[2], nq))
+    x = torch.from_numpy(xs).cuda()
+    ws = torch.empty(pr.pr_restrict_workspace_size(n, k), dtype=torch.uint8, device="cuda")
+    qp = torch.empty((k, nq + 1), dtype=torch.float64, device="cuda")
+    rank = torch.empty((k, n), dtype=torch.int32, device="cuda")
+    pr.pr_restrict_quantiles(x, pr.PR_F64, n, k, nq, qp, ws, rank=rank)
+    torch.cuda.synchronize()
+    assert np.array_equal(qp.cpu().numpy(), np.stack(qp_o))
+    qt = torch.from_numpy(np.stack(qt_o)).cuda()
+    q = torch.empty((k, nq + 1), dtype=torch.float64, device="cuda")
+    flag = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    pr.pr_match_knots(qt, qp, n, k, nq, ws, q, flag)
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    assert np.array_equal(q.cpu().numpy().view(np.uint64), np.stack(qref).view(np.uint64))
 
 
 @pytest.mark.parametrize("nq", [1, 7, 100, 1000])
