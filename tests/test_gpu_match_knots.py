@@ -225,3 +225,39 @@ def test_parareal_sorts_new_states_when_needed(torch_dev):
         assert pr.pr_parareal_knot_sorts(h) == 2
     finally:
         pr.pr_parareal_destroy(h)
+
+
+def test_parareal_fp32_knots_and_exactness(torch_dev):
+    """FP32 stepping in the driver: the new knots come from the fine results'
+    32-bit sort without a second sort and equal the sort of the states, and
+    after K iterations every state is the serial FP32 fine run bit for bit."""
+    torch = torch_dev
+    _say("parareal fp32")
+    n, K, nq, S = 5000, 6, 50, 600
+    sde = pr.Sde(lam=1.0, eps=0.1, beta=2.0, precision=pr.PR_F32)
+    sched = pr.Schedule(S, K, 1e-3)
+    h = pr.pr_parareal_create(sde, sched, pr.Grid(n_cells=100, n_q=nq), 0, 0, n, 0)
+    try:
+        x = torch.empty(n, dtype=torch.float32, device="cuda")
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        pr.pr_init_ensemble(sde, 0, 0, n, x, y)
+        ref = [x.clone()]
+        for s in range(K):
+            pr.pr_fine_propagate(sde, sched, 0, 0, n, s, 1, x, y)
+            ref.append(x.clone())
+        ws = torch.empty(pr.pr_restrict_workspace_size(n, 1, pr.PR_F32), dtype=torch.uint8, device="cuda")
+        for k in range(1, K + 1):
+            pr.pr_parareal_iterate(h, 1)
+            for t in range(K + 1):
+                xs = torch.empty(n, dtype=torch.float32, device="cuda")
+                q = torch.empty(nq + 1, dtype=torch.float64, device="cuda")
+                qs = torch.empty(nq + 1, dtype=torch.float64, device="cuda")
+                pr.pr_parareal_state(h, t, x=xs, q=q)
+                pr.pr_restrict_quantiles(xs, pr.PR_F32, n, 1, nq, qs, ws)
+                torch.cuda.synchronize()
+                assert torch.equal(q, qs), (k, t)
+                if t <= k:
+                    assert torch.equal(xs, ref[t]), (k, t)
+        assert pr.pr_parareal_knot_sorts(h) == 0
+    finally:
+        pr.pr_parareal_destroy(h)
