@@ -207,6 +207,23 @@ def test_restrict_identical_inputs(torch_dev, k, n):
         assert np.array_equal(out["hist"][s], OR.histogram(xs[s], 200, -3.0, 3.0)), s
 
 
+@pytest.mark.parametrize("k,n", [(5000, 3), (700, 65)])
+def test_restrict_many_small_segments(torch_dev, k, n):
+    """Thousands of ensembles of a few particles each (one partial tile per
+    segment, runs of equal high halves across the whole segment)."""
+    torch = torch_dev
+    _say(f"restrict many segments k={k} n={n}")
+    xs = inputs.slow_values(40 + k, k, n, ties=False)
+    xs[: k // 2, : min(n, 3)] = 0.25  # exact ties inside a segment
+    out = _restrict_gpu(torch, xs, 10)
+    for s in range(0, k, max(1, k // 97)):
+        perm, rank, srt = OR.sort_ranks(xs[s])
+        assert np.array_equal(out["perm"][s], perm), s
+        assert np.array_equal(out["rank"][s], rank), s
+        assert np.array_equal(out["xs"][s].view(np.uint64), srt.view(np.uint64)), s
+        assert np.array_equal(out["q"][s], OR.hazen_knots(srt, 10)), s
+
+
 def test_restrict_large_segments(torch_dev):
     torch = torch_dev
     n, k = 2 ** 20, 3
