@@ -7,8 +7,9 @@
 // Sort design (HBM bound): 8-bit digits, one pass per byte of the orderable
 // key.  A pass is
 //   count   digit histogram of every tile (ITEMS x 256 keys),
-//   rowscan one wave per (segment, digit): exclusive prefix of that digit's
-//           tile counts and the digit total of the segment,
+//   rowscan one wave per (segment, digit) -- one block per segment in the
+//           segment-table layout: exclusive prefix of that digit's tile
+//           counts and the digit total of the segment,
 //   scatter stable rank of every key inside its tile (each wave ranks its
 //           keys in order with ballot-built peer masks), exclusive scan of
 //           the digit totals, then the tile is staged in LDS in digit order
@@ -17,7 +18,11 @@
 // by (key, particle).  The first pass reads FP64 (or FP32) values directly
 // and generates the particle index as payload; the last pass writes the
 // outputs asked for (rank by scatter, perm and sorted values in order).  A
-// sort that only needs knots carries no payload.
+// sort that only needs knots carries no payload.  64-bit keys run only the
+// four passes over their high halves, then a fix-up pass (rs_fixup) that
+// orders every run of equal high halves and writes the last pass's outputs;
+// the complete sort follows, guarded by a flag that the fix-up raises only
+// for a run longer than it handles.
 #include <type_traits>
 
 #include "pr_internal.hpp"
