@@ -108,6 +108,27 @@ void or_box_muller(const uint32_t w[4], double *z0, double *z1)
     *z1 = r * sin(ang);
 }
 
+/*
+ * Normals of the single-precision fine propagator.  Reading: the same block
+ * cut to the bits a float carries, the top 24 bits of w0 for the radius and
+ * bits 4..31 of w2 for the angle:
+ *   u = (k + 1/2) 2^-24,  k = w0 >> 8                         u in (0, 1)
+ *   t = (i + f) / 128,    i = (w2 >> 4) mod 256, f = (w2 >> 12) 2^-20
+ * and the transform above.  Here u and t are exact and the transform runs in
+ * double precision: the law of the variant, without its float rounding.
+ */
+void or_box_muller_f32(const uint32_t w[4], double *z0, double *z1)
+{
+    uint32_t k = w[0] >> 8;
+    uint32_t i = (w[2] >> 4) & 255u;
+    double u = ((double)k + 0.5) * 0x1p-24;
+    double t = ((double)i + (double)(w[2] >> 12) * 0x1p-20) / 128.0;
+    double r = sqrt(-2.0 * log(u));
+    double ang = M_PI * t;
+    *z0 = r * cos(ang);
+    *z1 = r * sin(ang);
+}
+
 /* Normal pair j of (tag, m, p). */
 void or_normal_pair(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t m,
                     uint32_t p, uint32_t j, double *z0, double *z1)
@@ -115,6 +136,15 @@ void or_normal_pair(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t m,
     uint32_t w[4];
     or_block(seed, inst, tag, m, p, j, w);
     or_box_muller(w, z0, z1);
+}
+
+/* The same pair with the single-precision variant's normals. */
+static void or_normal_pair_f32(uint64_t seed, uint32_t inst, uint32_t tag, uint32_t m,
+                               uint32_t p, uint32_t j, double *z0, double *z1)
+{
+    uint32_t w[4];
+    or_block(seed, inst, tag, m, p, j, w);
+    or_box_muller_f32(w, z0, z1);
 }
 
 /* Normal number `idx` of (tag, m, p): index 2j is z0 of pair j, 2j+1 is z1. */
@@ -202,11 +232,12 @@ void or_init_ensemble(const or_sde *s, const double *a, uint64_t seed, uint32_t 
 /* Euler-Maruyama (Sec. 2.1.3, eq. (EMx)/(EMy)): drift at the old state,     */
 /* increments sqrt(dt) z with z from the noise layout above (tag 0, m = the  */
 /* global step index).  Advances particles [p0, p0+n) over global steps      */
-/* [m_begin, m_end).  x[n], y[d][n] in place.                                */
+/* [m_begin, m_end).  x[n], y[d][n] in place.  f32_noise selects the normals */
+/* of the single-precision propagator (the scheme itself stays in double).   */
 /* ------------------------------------------------------------------------ */
-void or_em_propagate(const or_sde *s, const double *a, uint64_t seed, uint32_t inst,
-                     int64_t p0, int64_t n, int64_t m_begin, int64_t m_end,
-                     double dt, double *x, double *y)
+static void em_propagate(const or_sde *s, const double *a, uint64_t seed, uint32_t inst,
+                         int64_t p0, int64_t n, int64_t m_begin, int64_t m_end,
+                         double dt, double *x, double *y, int f32_noise)
 {
     int d = s->d;
     double sx = sqrt(2.0 * dt / s->beta);
@@ -220,8 +251,12 @@ void or_em_propagate(const or_sde *s, const double *a, uint64_t seed, uint32_t i
         double xv = x[q];
         for (int i = 0; i < d; ++i) yv[i] = y[(int64_t)i * n + q];
         for (int64_t m = m_begin; m < m_end; ++m) {
-            for (int k = 0; k < d + 1; k += 2)
-                or_normal_pair(seed, inst, 0u, (uint32_t)m, p, (uint32_t)(k / 2), &z[k], &z[k + 1]);
+            for (int k = 0; k < d + 1; k += 2) {
+                if (f32_noise)
+                    or_normal_pair_f32(seed, inst, 0u, (uint32_t)m, p, (uint32_t)(k / 2), &z[k], &z[k + 1]);
+                else
+                    or_normal_pair(seed, inst, 0u, (uint32_t)m, p, (uint32_t)(k / 2), &z[k], &z[k + 1]);
+            }
             double ybar = 0.0;
             for (int i = 0; i < d; ++i) ybar += yv[i];
             ybar = ybar / (double)d;
@@ -238,6 +273,20 @@ void or_em_propagate(const or_sde *s, const double *a, uint64_t seed, uint32_t i
         free(z);
         free(yv);
     }
+}
+
+void or_em_propagate(const or_sde *s, const double *a, uint64_t seed, uint32_t inst,
+                     int64_t p0, int64_t n, int64_t m_begin, int64_t m_end,
+                     double dt, double *x, double *y)
+{
+    em_propagate(s, a, seed, inst, p0, n, m_begin, m_end, dt, x, y, 0);
+}
+
+void or_em_propagate_f32noise(const or_sde *s, const double *a, uint64_t seed, uint32_t inst,
+                              int64_t p0, int64_t n, int64_t m_begin, int64_t m_end,
+                              double dt, double *x, double *y)
+{
+    em_propagate(s, a, seed, inst, p0, n, m_begin, m_end, dt, x, y, 1);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -41,9 +41,12 @@ def lib():
         L.or_instance_params.argtypes = [u64, u32, P(dbl), P(dbl), P(i64), P(i32)]
         L.or_init_ensemble.argtypes = [P(_Sde), vp, u64, u32, i64, vp, vp]
         L.or_em_propagate.argtypes = [P(_Sde), vp, u64, u32, i64, i64, i64, i64, dbl, vp, vp]
+        L.or_em_propagate_f32noise.argtypes = L.or_em_propagate.argtypes
+        L.or_box_muller_f32.argtypes = [vp, vp, vp]
         L.or_em_tangent.argtypes = [P(_Sde), u64, u32, i64, i64, dbl, vp, vp, vp, vp]
-        for f in ("or_philox", "or_blocks", "or_normals", "or_box_muller", "or_coupling", "or_instance_params",
-                  "or_init_ensemble", "or_em_propagate", "or_em_tangent"):
+        for f in ("or_philox", "or_blocks", "or_normals", "or_box_muller", "or_box_muller_f32", "or_coupling",
+                  "or_instance_params", "or_init_ensemble", "or_em_propagate", "or_em_propagate_f32noise",
+                  "or_em_tangent"):
             getattr(L, f).restype = None
         _LIB = L
     return _LIB
@@ -89,15 +92,24 @@ def normals(seed, inst, tag, m, p0, n, n_norm):
     return out
 
 
-def box_muller(words):
-    """Normal pair of each block of words (rows of 4 x u32) -> (z0, z1)."""
+def _pairs(fn, words):
     w = np.ascontiguousarray(np.atleast_2d(words), dtype=np.uint32)
     z = np.zeros((len(w), 2), dtype=np.float64)
-    L = lib()
     for k in range(len(w)):
-        L.or_box_muller(w[k].ctypes.data_as(ctypes.c_void_p), z[k].ctypes.data_as(ctypes.c_void_p),
-                        ctypes.c_void_p(z[k].ctypes.data + 8))
+        fn(w[k].ctypes.data_as(ctypes.c_void_p), z[k].ctypes.data_as(ctypes.c_void_p),
+           ctypes.c_void_p(z[k].ctypes.data + 8))
     return z[:, 0], z[:, 1]
+
+
+def box_muller(words):
+    """Normal pair of each block of words (rows of 4 x u32) -> (z0, z1)."""
+    return _pairs(lib().or_box_muller, words)
+
+
+def box_muller_f32(words):
+    """The single-precision propagator's normal pair of each block (its
+    24- and 28-bit uniforms, transformed in double precision)."""
+    return _pairs(lib().or_box_muller_f32, words)
 
 
 def coupling(seed, inst, d):
@@ -124,14 +136,17 @@ def init_ensemble(sde, seed, inst, n):
     return x, y
 
 
-def em_propagate(sde, seed, inst, x, y, m_begin, m_end, dt, p0=0):
-    """Euler-Maruyama over global steps [m_begin, m_end); returns new (x, y)."""
+def em_propagate(sde, seed, inst, x, y, m_begin, m_end, dt, p0=0, f32_noise=False):
+    """Euler-Maruyama over global steps [m_begin, m_end); returns new (x, y).
+    f32_noise: the normals of the single-precision propagator, the scheme
+    still in double precision."""
     x = np.array(x, dtype=np.float64, copy=True, order="C")
     y = np.array(y, dtype=np.float64, copy=True, order="C").reshape(sde.d, -1)
     n = x.shape[0]
     a = sde.a
-    lib().or_em_propagate(ctypes.byref(sde.c()), None if a is None else _ptr(a), seed, inst,
-                          p0, n, m_begin, m_end, dt, _ptr(x), _ptr(y))
+    fn = lib().or_em_propagate_f32noise if f32_noise else lib().or_em_propagate
+    fn(ctypes.byref(sde.c()), None if a is None else _ptr(a), seed, inst, p0, n, m_begin, m_end, dt, _ptr(x),
+       _ptr(y))
     return x, y
 
 

@@ -166,6 +166,50 @@ def test_fine_fp32_error_vs_fp64_oracle(torch_dev):
     assert err < 0.02
 
 
+@pytest.mark.parametrize("d,n,S,K,dt,eps", [(1, 4_099, 300, 3, 1e-3, 0.1), (32, 700, 120, 2, 1e-4, 0.01),
+                                             (2, 257, 50, 5, 1e-3, 0.05)])
+def test_fine_fp32_per_particle(torch_dev, d, n, S, K, dt, eps):
+    """FP32 stepping particle by particle against the oracle run with the
+    same normals (the 24- and 28-bit uniforms of the same words) in double
+    precision.  They differ only by float rounding: per step at most six
+    roundings of the state (6 * 2^-24 per unit of |state|) and the float
+    transform's error (a few 2^-24 of |z| <= 5.9, times sqrt(2 dt/beta) or
+    sqrt(2 dt/(beta eps)) <= 0.1), under 5e-7 per unit, grown by at most
+    e^{2T} < 1.9 along a slice of T <= 0.3; so 1e-6 per step and unit.  The
+    rounding of u = (k + 1/2) 2^-24 to a float moves the radius by up to
+    2^-12 / sqrt(2) for the rare u within a few 2^-24 of 1: 2e-5 more after
+    the factor 0.1.  A wrong bit, word, coefficient or sign moves a particle
+    by ~sqrt(2 dt/beta) = 0.03 (or 0.01 for dt = 1e-4) in one step."""
+    torch = torch_dev
+    _say(f"fine fp32 d={d} n={n} S={S} K={K}")
+    a_np = OP.coupling(0, 0, d) if d > 1 else None
+    so = OP.Sde(lam=1.0, eps=eps, beta=2.0, d=d, a=a_np)
+    x0, y0 = OP.init_ensemble(so, 0, 0, n)
+    xs = np.stack([x0 + 0.1 * k for k in range(K)]).astype(np.float32)
+    ys = np.stack([y0 - 0.05 * k for k in range(K)]).astype(np.float32)
+    x = torch.from_numpy(xs.copy()).cuda()
+    y = torch.from_numpy(ys.copy()).cuda()
+    a = torch.from_numpy(a_np).cuda() if a_np is not None else None
+    sde = pr.Sde(lam=1.0, eps=eps, beta=2.0, d=d, a=a, precision=pr.PR_F32)
+    pr.pr_fine_propagate(sde, pr.Schedule(S, K, dt), 0, 0, n, 0, K, x, y)
+    _sync(torch)
+    xg, yg = x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
+    b = OI.slice_bounds(S, K)
+    worst = 0.0
+    for k in range(K):
+        xr, yr = OP.em_propagate(so, 0, 0, xs[k].astype(np.float64), ys[k].astype(np.float64), b[k], b[k + 1], dt,
+                                 f32_noise=True)
+        steps = b[k + 1] - b[k]
+        scale = max(1.0, np.abs(xr).max(), np.abs(yr).max())
+        tol = 1e-6 * steps * scale + 2e-5
+        ex, ey = np.abs(xg[k] - xr).max(), np.abs(yg[k] - yr).max()
+        worst = max(worst, ex / tol, ey / tol)
+        assert ex < tol and ey < tol, (k, ex, ey, tol)
+        # the typical particle is much closer: rounding errors of both signs
+        assert np.sqrt(np.mean((xg[k] - xr) ** 2)) < 1e-6 * np.sqrt(steps) * scale, k
+    _say(f"fp32 per particle: worst error / tolerance = {worst:.3e}")
+
+
 # ---------------------------------------------------------------------------
 # restriction
 # ---------------------------------------------------------------------------

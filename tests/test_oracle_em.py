@@ -151,3 +151,43 @@ def test_effective_potential_cases():
     V2 = C.effective_potential(s2)
     # abar = 0.75: extra lambda (1 - abar) x^2 / 2 = 0.0625 x^2
     assert abs(V2(2.0) - (4.0 - 2.0 + 0.25)) < 1e-15
+
+
+def test_f32_noise_pure_diffusion_increments(oracle_lib):
+    """With every drift coefficient zero (c3 = c1 = lambda = 0, Y started at
+    X with a = 1) one step moves X by sqrt(2 dt/beta) z0 and Y by
+    sqrt(2 dt/(beta eps)) z1, z from the single-precision propagator's normals
+    of the block (tag 0, step m, particle p, pair 0); pair 1 drives Y_2."""
+    n, m, dt = 64, 37, 1e-3
+    for d in (1, 2):
+        s = P.Sde(lam=0.0, eps=0.05, beta=2.0, c3=0.0, c1=0.0, d=d)
+        x0 = np.linspace(-1.0, 1.0, n)
+        y0 = np.tile(x0, (d, 1))
+        x, y = P.em_propagate(s, 5, 2, x0, y0, m, m + 1, dt, p0=11, f32_noise=True)
+        z0, z1 = P.box_muller_f32(P.blocks(5, 2, 0, m, 11, n, j=0))
+        assert np.abs((x - x0) / np.sqrt(2 * dt / s.beta) - z0).max() < 1e-9
+        assert np.abs((y[0] - y0[0]) / np.sqrt(2 * dt / (s.beta * s.eps)) - z1).max() < 1e-9
+        if d == 2:
+            w0, _ = P.box_muller_f32(P.blocks(5, 2, 0, m, 11, n, j=1))
+            assert np.abs((y[1] - y0[1]) / np.sqrt(2 * dt / (s.beta * s.eps)) - w0).max() < 1e-9
+        # the double-precision normals are other numbers
+        xd, _ = P.em_propagate(s, 5, 2, x0, y0, m, m + 1, dt, p0=11)
+        assert np.abs(xd - x).max() > 1e-10
+
+
+def test_f32_noise_ou_closed_form(oracle_lib):
+    """The single-precision propagator's normals drive the scheme with the
+    exact moment recursion of the linear case, as the double ones do."""
+    n, steps, dt = 200_000, 300, 2e-3
+    s = P.Sde(lam=0.7, eps=0.05, beta=1.5, c3=0.0, c1=1.0)
+    x0, y0 = P.init_ensemble(s, 3, 0, n)
+    x, y = P.em_propagate(s, 3, 0, x0 + 0.8, y0 + 0.8, 0, steps, dt, f32_noise=True)
+    m0 = np.array([0.8, 0.8])
+    S0 = np.array([[0.25, 0.25], [0.25, 0.25 + 1 / s.beta]])
+    m, S = _ou_moments(s.lam, s.eps, s.beta, s.c1, dt, steps, m0, S0)
+    z = np.vstack([x, y[0]])
+    assert np.all(np.abs(z.mean(1) - m) < 5 * np.sqrt(np.diag(S) / n))
+    cov = np.cov(z)
+    se = np.sqrt((S ** 2 + np.outer(np.diag(S), np.diag(S))) / n)
+    assert np.all(np.abs(cov - S) < 5 * se)
+    assert st.kstest(x, "norm", args=(m[0], np.sqrt(S[0, 0]))).statistic < 1.63 / np.sqrt(n)

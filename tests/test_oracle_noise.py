@@ -149,6 +149,70 @@ def test_box_muller_angle_cells_uniform(oracle_lib):
     assert abs(np.corrcoef(r2, cell)[0, 1]) < 5.0 / np.sqrt(n)
 
 
+def test_box_muller_f32_bit_layout_closed_forms(oracle_lib):
+    """Normals of the single-precision propagator: u = (k + 1/2) 2^-24 from the
+    top 24 bits of w0, the angle pi t with t = (i + f)/128, i from bits 4..11
+    of w2 and f from bits 12..31 of w2 (20 bits); w1, w3 and the low bits of
+    w0 and w2 take no part."""
+    M = 0xFFFFFFFF
+    r_min_u = np.sqrt(50.0 * np.log(2.0))           # u = 2^-25
+    cases = [
+        ((0, 0, 0, 0), r_min_u, 0.0),
+        ((0, 0, 64 << 4, 0), 0.0, r_min_u),             # t = 1/2
+        ((0, 0, 128 << 4, 0), -r_min_u, 0.0),           # t = 1
+        ((0, 0, 192 << 4, 0), 0.0, -r_min_u),           # t = 3/2
+        ((0, 0, 0x80000000, 0), r_min_u * np.cos(np.pi / 256), r_min_u * np.sin(np.pi / 256)),  # f = 1/2
+        ((0, 0, 0xF, 0), r_min_u, 0.0),                 # bits 0..3 of w2 are unused
+        ((0xFF, 0, 0, 0), r_min_u, 0.0),                # bits 0..7 of w0 are unused
+        ((0, M, 0, M), r_min_u, 0.0),                   # w1 and w3 are unused
+    ]
+    for w, e0, e1 in cases:
+        z0, z1 = P.box_muller_f32(np.array(w, dtype=np.uint32))
+        assert abs(z0[0] - e0) < 4e-15 and abs(z1[0] - e1) < 4e-15, (w, z0, z1, e0, e1)
+    # u = 1 - 2^-25 (largest): radius sqrt(-2 ln(1 - 2^-25)) = 2^-12 (1 + 2^-27 + ...)
+    z0, _ = P.box_muller_f32(np.array((M, 0, 0, 0), dtype=np.uint32))
+    assert abs(z0[0] / 2.0 ** -12 - 1.0) < 1e-8
+    # k = 1 (bit 8 of w0): u = 3 * 2^-25
+    z0, _ = P.box_muller_f32(np.array((0x100, 0, 0, 0), dtype=np.uint32))
+    assert abs(z0[0] - np.sqrt(-2.0 * np.log(3.0 * 2.0 ** -25))) < 1e-14
+    # bit 12 of w2 is the lowest bit of f: f = 2^-20 moves the angle by pi 2^-27
+    _, z1 = P.box_muller_f32(np.array((0, 0, 1 << 12, 0), dtype=np.uint32))
+    assert abs(z1[0] - r_min_u * np.sin(np.pi * 2.0 ** -27)) < 1e-22
+
+
+def test_box_muller_f32_is_the_double_transform_of_its_bits(oracle_lib):
+    """The single-precision normals are the double-precision transform of a
+    block that carries the same bits: with w1 = (bits 8..11 of w0) 2^28 +
+    2^27 and w3 = 0, the double transform's u is the single one's plus
+    2^-53 and its angle is the same, so the pairs agree to
+    2^-53 / (u r) <= 2^-28 / 5.89 < 1e-9 (u >= 2^-25)."""
+    rng = np.random.default_rng(77)
+    w = rng.integers(0, 2 ** 32, (4000, 4), dtype=np.uint64).astype(np.uint32)
+    w[:3, 0] = [0, 0xFFFFFFFF, 0x80000000]
+    a0, a1 = P.box_muller_f32(w)
+    wd = w.copy()
+    wd[:, 1] = (((w[:, 0] >> 8) & 0xF) << 28) | (1 << 27)
+    wd[:, 3] = 0
+    b0, b1 = P.box_muller(wd)
+    assert np.abs(a0 - b0).max() < 1e-9 and np.abs(a1 - b1).max() < 1e-9
+    # and differs from the full-width pair of the original words (the bits
+    # below the top 24 of u matter there)
+    c0, _ = P.box_muller(w)
+    assert np.abs(a0 - c0).max() > 1e-7
+
+
+def test_box_muller_f32_distribution(oracle_lib):
+    n = 200_000
+    b = P.blocks(4, 0, 0, 9, 0, n)
+    z0, z1 = P.box_muller_f32(b)
+    for v in (z0, z1):
+        assert abs(v.mean()) < 5.0 / np.sqrt(n)
+        assert abs(v.var() - 1.0) < 5.0 * np.sqrt(2.0 / n)
+        assert st.kstest(v, "norm").statistic < 1.63 / np.sqrt(n)
+    assert abs(np.corrcoef(z0, z1)[0, 1]) < 5.0 / np.sqrt(n)
+    assert np.abs(np.hypot(z0, z1)).max() <= np.sqrt(50.0 * np.log(2.0)) + 1e-12
+
+
 def test_coupling_and_instance_params(oracle_lib):
     a = P.coupling(0, 0, 32)
     assert a.shape == (32,) and np.all(a >= 0.5) and np.all(a < 1.5)
