@@ -512,6 +512,17 @@ def main():
                           basis=f"{VALU_OPS_PER_STEP} VALU instructions per particle-step at "
                                 f"{VALU_PEAK / 1e12:.1f} T lane-instructions/s, 40 B per particle and slice at 8 TB/s")
 
+    # the HBM-bound phases against the bytes the method must move per particle
+    # and slice: the restriction's key read and rank write (12 B; a sort
+    # moves several times that, and its counted bytes are in the profiles),
+    # the matching's state read, rank read and state write (20 B), and the
+    # sorted-key read behind the knots of the new states (8 B)
+    hbm_phases = {}
+    for name, per in (("restrict_fine", 12), ("match", 20), ("restrict_new", 8)):
+        b = n * K * per
+        t = phases[name] * 1e-3
+        hbm_phases[name] = dict(bytes=b, ms=phases[name], achieved_gbs=b / t / 1e9, frac=b / t / HBM_PEAK)
+
     out = dict(metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
@@ -521,6 +532,7 @@ def main():
                            cells=w["cells"], quantile_levels=nq, flags=args.flags, seed=w["seed"]),
                roofline=roofline,
                sweep_roofline=sweep_roofline,
+               hbm_phases=hbm_phases,
                phases_ms=phases,
                quantile_error=dict(at_T=[float(errs[2 * i]) for i in range(args.warmup + args.steps)],
                                    max_over_slices=[float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]),
