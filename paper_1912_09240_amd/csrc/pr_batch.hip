@@ -310,7 +310,7 @@ struct Batch {
     // sorts: fine results (t = 1..K_i of every instance) and time 0
     SortSeg *seg_f = nullptr;
     int *tile_f = nullptr;
-    int64_t tiles_f = 0, keys_f = 0;
+    int64_t tiles_f = 0, keys_f = 0, seg_max_n = 0;
     std::vector<SortSeg> seg_f_h;
     // matching
     MatchSeg *mseg = nullptr;
@@ -490,7 +490,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
     const GridDev &g = b->g;
     if (mode == 0) {
         PR_CHECK(fine_batch(b, b->n_units, c, nx, st));
-        SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f};
+        SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
         PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, Q, b->qf, b->rank, b->ws, st));
         const double *cin = (b->flags & PR_REUSE_COARSE) ? b->q : b->qR;
         hipLaunchKernelGGL(k2m_units, dim3(b->total_slices), dim3(256), sizeof(double) * (g.nq + g.cells + 2), st,
@@ -700,6 +700,7 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
             b->seg_f_h.push_back(g);
             tiles += g.nblk;
             keys += n[i];
+            b->seg_max_n = std::max(b->seg_max_n, (int64_t)n[i]);
         }
     b->tiles_f = tiles;
     b->keys_f = keys;

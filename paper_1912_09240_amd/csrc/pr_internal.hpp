@@ -253,6 +253,7 @@ struct SortLayout {
     const SortSeg *segs;   // unequal lengths: device table [nseg]
     const int *tile_seg;   // unequal lengths: device table [tiles]
     const int *guard;      // device flag or NULL: while it reads 0 every kernel of the sort returns at once
+    int64_t max_n;         // unequal lengths: the longest segment (0 if not known)
 };
 int64_t sort_tiles(int64_t n);
 size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload);

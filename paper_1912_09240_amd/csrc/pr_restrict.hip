@@ -20,9 +20,10 @@
 // outputs asked for (rank by scatter, perm and sorted values in order).  A
 // sort that only needs knots carries no payload.  64-bit keys run only the
 // four passes over their high halves, then a fix-up pass (rs_fixup) that
-// orders every run of equal high halves and writes the last pass's outputs;
-// the complete sort follows, guarded by a flag that the fix-up raises only
-// for a run longer than it handles.
+// orders every run of equal high halves and writes the last pass's outputs
+// (the ranks through a staging buffer instead of stores to random addresses,
+// rs_rank_bucket and rs_rank_place); the complete sort follows, guarded by a
+// flag that the fix-up raises only for a run longer than it handles.
 #include <type_traits>
 
 #include "pr_internal.hpp"
@@ -490,6 +491,104 @@ rs_fixup(const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ vals
         }
     }
     if (too_long) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Ranks from the permutation (sorted position -> particle) without stores to
+// random addresses: a 4-byte store at a random index leaves its cache line
+// partly written, and the line then costs a whole memory sector.  Instead
+//   rs_rank_bucket  every tile of the permutation groups its (position,
+//                   particle) pairs by the block of TILE particles the
+//                   particle belongs to and appends each group, as one
+//                   contiguous run, to that block's region of a staging
+//                   buffer (the region has one slot per particle of the
+//                   block; a cursor per block hands out the slots),
+//   rs_rank_place   every block of TILE particles takes its region, places
+//                   the ranks in LDS and writes them out in particle order.
+// A pair packs the position (below 2^20) and the particle's offset in its
+// block (below 2^12) into 32 bits, so segments of up to 2^20 keys take this
+// path.  Both kernels return at once where the fix-up raised its flag (the
+// complete sort then writes the ranks).
+// ---------------------------------------------------------------------------
+constexpr int RK_SHIFT = 12;
+constexpr int64_t RK_MAX_N = (int64_t)1 << 20;
+static_assert((1 << RK_SHIFT) == RS_THREADS * RS_ITEMS, "a block of particles is one tile");
+static_assert(RS_THREADS == RS_RADIX, "one thread per particle block of a segment");
+
+template <bool VAR>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_rank_bucket(const uint32_t *__restrict__ perm, SortLayout L, uint32_t *__restrict__ cursor,
+               uint32_t *__restrict__ staged, const int *__restrict__ flag) {
+    constexpr int TILE = RS_THREADS * RS_ITEMS;
+    __shared__ uint32_t cnt[RS_RADIX], lofs[RS_RADIX], gofs[RS_RADIX], wtot[RS_WAVES];
+    __shared__ uint32_t stage[TILE];
+    __shared__ uint8_t sblk[TILE];
+    if ((L.guard && *L.guard == 0) || *flag != 0) return;
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const int tid = threadIdx.x;
+    cnt[tid] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)T.blk * TILE;
+    uint32_t p[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t pos = t0 + (int64_t)i * RS_THREADS + tid;
+        p[i] = pos < T.n ? perm[T.base + pos] : 0xFFFFFFFFu;
+    }
+    uint32_t slot[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i)
+        if ((int64_t)p[i] < T.n) slot[i] = atomicAdd(&cnt[p[i] >> RK_SHIFT], 1u);
+    __syncthreads();
+    const uint32_t c = cnt[tid];
+    lofs[tid] = block_exclusive_256(c, wtot);
+    if (c != 0) gofs[tid] = atomicAdd(&cursor[T.tile0 + tid], c);  // c != 0 only for blocks of this segment
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        if ((int64_t)p[i] < T.n) {
+            const uint32_t b = p[i] >> RK_SHIFT, j = lofs[b] + slot[i];
+            const uint32_t pos = (uint32_t)(t0 + i * RS_THREADS + tid);
+            stage[j] = (pos << RK_SHIFT) | (p[i] & (TILE - 1));
+            sblk[j] = (uint8_t)b;
+        }
+    }
+    __syncthreads();
+    const uint32_t total = lofs[RS_RADIX - 1] + cnt[RS_RADIX - 1];
+    for (uint32_t j = tid; j < total; j += RS_THREADS) {
+        const uint32_t b = sblk[j];
+        const int64_t b0 = (int64_t)b << RK_SHIFT;
+        const int64_t bn = T.n - b0 < TILE ? T.n - b0 : TILE;
+        const uint32_t s = gofs[b] + (j - lofs[b]);
+        if ((int64_t)s < bn) staged[T.base + b0 + s] = stage[j];
+    }
+}
+
+template <bool VAR>
+__global__ void __launch_bounds__(RS_THREADS)
+rs_rank_place(const uint32_t *__restrict__ staged, SortLayout L, uint32_t *__restrict__ rank_out,
+              const int *__restrict__ flag) {
+    constexpr int TILE = RS_THREADS * RS_ITEMS;
+    __shared__ uint32_t r[TILE];
+    if ((L.guard && *L.guard == 0) || *flag != 0) return;
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const int64_t b0 = (int64_t)T.blk * TILE;
+    const int bn = (int)(T.n - b0 < TILE ? T.n - b0 : TILE);
+    uint32_t e[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int j = i * RS_THREADS + threadIdx.x;
+        e[i] = j < bn ? staged[T.base + b0 + j] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i)
+        if (i * RS_THREADS + (int)threadIdx.x < bn && (int)(e[i] & (TILE - 1)) < bn) r[e[i] & (TILE - 1)] = e[i] >> RK_SHIFT;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int j = i * RS_THREADS + threadIdx.x;
+        if (j < bn) rank_out[T.base + b0 + j] = r[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -975,13 +1074,32 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
         for (int j = 0; j < 4; ++j) PR_CHECK(pass(L, 32 + 8 * j, j == 0, false, (j + 1) & 1, j & 1, true));
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
         PR_LAUNCHED();
+        // ranks through the staging buffer (vals[1], free once the fix-up
+        // has read it) where every segment fits the packing, the fix-up
+        // then writing the permutation in order (into vals[0] unless asked
+        // for) instead of the ranks
+        const int64_t max_n = VAR ? L.max_n : L.n;
+        const bool staged_ranks = rank != nullptr && max_n > 0 && max_n <= RK_MAX_N;
+        uint32_t *perm_fix = perm ? perm : (staged_ranks ? vals[0] : nullptr);
         if (payload)
             hipLaunchKernelGGL((rs_fixup<VAR, true>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
-                               (const uint32_t *)vals[1], (uint64_t *)keys[0], L, rank, perm, xs, flag);
+                               (const uint32_t *)vals[1], (uint64_t *)keys[0], L, staged_ranks ? nullptr : rank,
+                               perm_fix, xs, flag);
         else
             hipLaunchKernelGGL((rs_fixup<VAR, false>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
                                (const uint32_t *)nullptr, (uint64_t *)keys[0], L, rank, perm, xs, flag);
         PR_LAUNCHED();
+        if (staged_ranks) {
+            const int64_t zb = (total_tiles + 255) / 256 < 1024 ? (total_tiles + 255) / 256 : 1024;
+            hipLaunchKernelGGL(zero_u32, dim3((unsigned)zb), dim3(256), 0, st, counts, total_tiles);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL((rs_rank_bucket<VAR>), grid, dim3(RS_THREADS), 0, st, (const uint32_t *)perm_fix, L,
+                               counts, vals[1], (const int *)flag);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL((rs_rank_place<VAR>), grid, dim3(RS_THREADS), 0, st, (const uint32_t *)vals[1], L,
+                               rank, (const int *)flag);
+            PR_LAUNCHED();
+        }
         SortLayout LG = L;
         LG.guard = flag;
         for (int j = 0; j < P; ++j) PR_CHECK(pass(LG, 8 * j, j == 0, j == P - 1, j & 1, (j + 1) & 1, false));

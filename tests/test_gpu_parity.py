@@ -268,6 +268,29 @@ def test_restrict_many_small_segments(torch_dev, k, n):
         assert np.array_equal(out["q"][s], OR.hazen_knots(srt, 10)), s
 
 
+@pytest.mark.parametrize("k,n,ties", [(1, 1, False), (3, 4097, False), (4, 70_001, True), (2, 2 ** 20, False),
+                                      (2, 2 ** 20, True), (1, 2 ** 20 + 1, False)])
+def test_restrict_rank_only(torch_dev, k, n, ties):
+    """Ranks asked for alone, as the parareal drivers do: up to 2^20 keys per
+    segment they go through the staging buffer, beyond by direct stores; the
+    runs of hundreds of signed zeros of ties=True hand the ranks to the
+    complete sort."""
+    torch = torch_dev
+    _say(f"restrict rank only k={k} n={n} ties={ties}")
+    xs = inputs.slow_values(300 + n % 1000, k, n, ties=ties)
+    x = torch.from_numpy(xs).cuda()
+    ws = torch.empty(pr.pr_restrict_workspace_size(n, k, pr.PR_F64), dtype=torch.uint8, device="cuda")
+    q = torch.empty((k, 11), dtype=torch.float64, device="cuda")
+    rank = torch.empty((k, n), dtype=torch.int32, device="cuda")
+    pr.pr_restrict_quantiles(x, pr.PR_F64, n, k, 10, q, ws, rank=rank)
+    torch.cuda.synchronize()
+    rk, qg = rank.cpu().numpy().view(np.uint32), q.cpu().numpy()
+    for s in range(k):
+        _, ref, srt = OR.sort_ranks(xs[s])
+        assert np.array_equal(rk[s], ref), s
+        assert np.array_equal(qg[s], OR.hazen_knots(srt, 10)), s
+
+
 def test_restrict_large_segments(torch_dev):
     torch = torch_dev
     n, k = 2 ** 20, 3
