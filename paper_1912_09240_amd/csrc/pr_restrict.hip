@@ -1031,6 +1031,24 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
     if (payload) flag = (int *)((char *)vals[1] + align256(total_keys * 4));
     const dim3 grid((unsigned)total_tiles);
     const dim3 rows((unsigned)(((int64_t)L.nseg * RS_RADIX + 3) / 4));
+    // outputs of the last pass (the ranks move to the staging kernels below
+    // where they take over)
+    uint32_t *rank_last = rank, *perm_last = perm;
+    const int64_t max_n = VAR ? L.max_n : L.n;
+    const bool staged_ranks = rank != nullptr && max_n > 0 && max_n <= RK_MAX_N;
+    // ranks from the permutation in order, through the staging buffer
+    auto stage_ranks = [&](const uint32_t *perm_in, uint32_t *staging) -> int {
+        const int64_t zb = (total_tiles + 255) / 256 < 1024 ? (total_tiles + 255) / 256 : 1024;
+        hipLaunchKernelGGL(zero_u32, dim3((unsigned)zb), dim3(256), 0, st, counts, total_tiles);
+        PR_LAUNCHED();
+        hipLaunchKernelGGL((rs_rank_bucket<VAR>), grid, dim3(RS_THREADS), 0, st, perm_in, L, counts, staging,
+                           (const int *)flag);
+        PR_LAUNCHED();
+        hipLaunchKernelGGL((rs_rank_place<VAR>), grid, dim3(RS_THREADS), 0, st, (const uint32_t *)staging, L, rank,
+                           (const int *)flag);
+        PR_LAUNCHED();
+        return PR_OK;
+    };
     // One LSD pass over the byte at shift: keys[in] -> keys[out] (pass 0
     // reads the values), with the statistics on the first read and the rank,
     // perm and sorted-value outputs on the last pass.
@@ -1052,7 +1070,7 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
 #define PR_SCATTER(FIRST, LAST, PAY, SRC, VIN, VOUT)                                                            \
     hipLaunchKernelGGL((rs_scatter<K, ITEMS, FIRST, LAST, PAY, VAR>), grid, dim3(RS_THREADS), 0, st, SRC, VIN,     \
                        keys[out], VOUT, (const uint32_t *)counts, (const uint32_t *)totals, shift, LL,         \
-                       LAST ? rank : nullptr, LAST ? perm : nullptr, LAST ? xs : nullptr)
+                       LAST ? rank_last : nullptr, LAST ? perm_last : nullptr, LAST ? xs : nullptr)
         if (payload) {
             if (first) PR_SCATTER(true, false, true, x, nullptr, vals[out]);
             else if (!last) PR_SCATTER(false, false, true, (const void *)keys[in], vals[in], vals[out]);
@@ -1077,9 +1095,8 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
         // ranks through the staging buffer (vals[1], free once the fix-up
         // has read it) where every segment fits the packing, the fix-up
         // then writing the permutation in order (into vals[0] unless asked
-        // for) instead of the ranks
-        const int64_t max_n = VAR ? L.max_n : L.n;
-        const bool staged_ranks = rank != nullptr && max_n > 0 && max_n <= RK_MAX_N;
+        // for) instead of the ranks; the complete sort behind it keeps
+        // storing the ranks itself
         uint32_t *perm_fix = perm ? perm : (staged_ranks ? vals[0] : nullptr);
         if (payload)
             hipLaunchKernelGGL((rs_fixup<VAR, true>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
@@ -1089,22 +1106,23 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
             hipLaunchKernelGGL((rs_fixup<VAR, false>), grid, dim3(RS_THREADS), 0, st, (const uint64_t *)keys[1],
                                (const uint32_t *)nullptr, (uint64_t *)keys[0], L, rank, perm, xs, flag);
         PR_LAUNCHED();
-        if (staged_ranks) {
-            const int64_t zb = (total_tiles + 255) / 256 < 1024 ? (total_tiles + 255) / 256 : 1024;
-            hipLaunchKernelGGL(zero_u32, dim3((unsigned)zb), dim3(256), 0, st, counts, total_tiles);
-            PR_LAUNCHED();
-            hipLaunchKernelGGL((rs_rank_bucket<VAR>), grid, dim3(RS_THREADS), 0, st, (const uint32_t *)perm_fix, L,
-                               counts, vals[1], (const int *)flag);
-            PR_LAUNCHED();
-            hipLaunchKernelGGL((rs_rank_place<VAR>), grid, dim3(RS_THREADS), 0, st, (const uint32_t *)vals[1], L,
-                               rank, (const int *)flag);
-            PR_LAUNCHED();
-        }
+        if (staged_ranks) PR_CHECK(stage_ranks(perm_fix, vals[1]));
         SortLayout LG = L;
         LG.guard = flag;
         for (int j = 0; j < P; ++j) PR_CHECK(pass(LG, 8 * j, j == 0, j == P - 1, j & 1, (j + 1) & 1, false));
     } else {
+        // the last pass reads vals[0] and writes the permutation into vals[1]
+        // (unless asked for); vals[0] then stages the ranks
+        if (staged_ranks) {
+            rank_last = nullptr;
+            perm_last = perm ? perm : vals[1];
+        }
         for (int j = 0; j < P; ++j) PR_CHECK(pass(L, 8 * j, j == 0, j == P - 1, (j + 1) & 1, j & 1, true));
+        if (staged_ranks) {
+            hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
+            PR_LAUNCHED();
+            PR_CHECK(stage_ranks(perm_last, vals[0]));
+        }
     }
     const K *sorted = keys[sorted_buffer<K>()];
     hipLaunchKernelGGL((rs_knots<K, VAR>), dim3(L.nseg), dim3(128), 0, st, sorted, L, nq, q);

@@ -268,25 +268,30 @@ def test_restrict_many_small_segments(torch_dev, k, n):
         assert np.array_equal(out["q"][s], OR.hazen_knots(srt, 10)), s
 
 
-@pytest.mark.parametrize("k,n,ties", [(1, 1, False), (3, 4097, False), (4, 70_001, True), (2, 2 ** 20, False),
-                                      (2, 2 ** 20, True), (1, 2 ** 20 + 1, False)])
-def test_restrict_rank_only(torch_dev, k, n, ties):
+@pytest.mark.parametrize("k,n,ties,prec", [(1, 1, False, pr.PR_F64), (3, 4097, False, pr.PR_F64),
+                                           (4, 70_001, True, pr.PR_F64), (2, 2 ** 20, False, pr.PR_F64),
+                                           (2, 2 ** 20, True, pr.PR_F64), (1, 2 ** 20 + 1, False, pr.PR_F64),
+                                           (3, 4097, True, pr.PR_F32), (2, 2 ** 20, False, pr.PR_F32),
+                                           (1, 2 ** 20 + 1, True, pr.PR_F32)])
+def test_restrict_rank_only(torch_dev, k, n, ties, prec):
     """Ranks asked for alone, as the parareal drivers do: up to 2^20 keys per
-    segment they go through the staging buffer, beyond by direct stores; the
-    runs of hundreds of signed zeros of ties=True hand the ranks to the
-    complete sort."""
+    segment they go through the staging buffer, beyond by direct stores; for
+    FP64 keys the runs of hundreds of signed zeros of ties=True hand the
+    ranks to the complete sort."""
     torch = torch_dev
-    _say(f"restrict rank only k={k} n={n} ties={ties}")
+    _say(f"restrict rank only k={k} n={n} ties={ties} precision={prec}")
     xs = inputs.slow_values(300 + n % 1000, k, n, ties=ties)
+    if prec == pr.PR_F32:
+        xs = xs.astype(np.float32)
     x = torch.from_numpy(xs).cuda()
-    ws = torch.empty(pr.pr_restrict_workspace_size(n, k, pr.PR_F64), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(pr.pr_restrict_workspace_size(n, k, prec), dtype=torch.uint8, device="cuda")
     q = torch.empty((k, 11), dtype=torch.float64, device="cuda")
     rank = torch.empty((k, n), dtype=torch.int32, device="cuda")
-    pr.pr_restrict_quantiles(x, pr.PR_F64, n, k, 10, q, ws, rank=rank)
+    pr.pr_restrict_quantiles(x, prec, n, k, 10, q, ws, rank=rank)
     torch.cuda.synchronize()
     rk, qg = rank.cpu().numpy().view(np.uint32), q.cpu().numpy()
     for s in range(k):
-        _, ref, srt = OR.sort_ranks(xs[s])
+        _, ref, srt = OR.sort_ranks(xs[s].astype(np.float64))
         assert np.array_equal(rk[s], ref), s
         assert np.array_equal(qg[s], OR.hazen_knots(srt, 10)), s
 
