@@ -20,6 +20,7 @@ recorded on the stream it runs on.  The CPU baseline is the plain oracle
 running one iteration of the same workload on a bounded particle sample.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -80,24 +81,50 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n_sample):
     """One parareal iteration of the workload by the oracle, on particles
-    0..n_sample-1 (counter-based noise makes the sample exact)."""
+    0..n_sample-1 (counter-based noise makes the sample exact), on the
+    process's OpenMP threads; then on one thread, on an eighth of the
+    sample."""
     from oracle import coarse as OC
     from oracle import iterate as OI
     from oracle import particles as OP
     w = WORKLOAD
     sde = OP.Sde(lam=w["lam"], eps=w["eps"], beta=w["beta"])
-    po, hp = OI.micmac_parareal(sde, w["seed"], 0, n_sample, w["T"], w["dt"], w["K"], OC.Grid(w["cells"]), w["nq"])
-    t0 = time.perf_counter()
-    po.iterate()
-    t = time.perf_counter() - t0
-    S = hp["S"]
+
+    def one_iteration(n):
+        po, hp = OI.micmac_parareal(sde, w["seed"], 0, n, w["T"], w["dt"], w["K"], OC.Grid(w["cells"]), w["nq"])
+        t0 = time.perf_counter()
+        po.iterate()
+        return n * hp["S"], time.perf_counter() - t0
+
+    steps, t = one_iteration(n_sample)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=n_sample * S / t, unit="particle-steps/s", cores=threads, kind="oracle",
-                sample=f"one parareal iteration (fine propagation of all {w['K']} slices, restriction, coarse "
-                       f"propagation, quantile-iterator chain, matching) of the large workload on particles "
-                       f"0..{n_sample - 1}; {t:.2f} s on {threads} OpenMP threads")
+    out = dict(value=steps / t, unit="particle-steps/s", cores=threads, kind="oracle",
+               sample=f"one parareal iteration (fine propagation of all {w['K']} slices, restriction, coarse "
+                      f"propagation, quantile-iterator chain, matching) of the large workload on particles "
+                      f"0..{n_sample - 1}; {t:.2f} s on {threads} OpenMP threads",
+               cpu_model=_cpu_model(), nproc=os.cpu_count())
+    set_threads = getattr(OP.lib(), "omp_set_num_threads", None)
+    if set_threads is not None and threads > 1:
+        set_threads.argtypes = [ctypes.c_int]
+        set_threads(1)
+        n1 = max(64, n_sample // 8)
+        steps1, t1 = one_iteration(n1)
+        set_threads(threads)
+        out["one_thread"] = dict(value=steps1 / t1, sample=f"particles 0..{n1 - 1}, {t1:.2f} s on one OpenMP thread")
+    return out
 
 
 ADJOINT = dict(lam=1.0, beta=2.0, eps=0.1, c3=1.0, n=2 ** 20, S=10_000, dt=1e-4, every=256, seed=0,
