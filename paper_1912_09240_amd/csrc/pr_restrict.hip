@@ -302,18 +302,28 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
     K key[ITEMS];
     uint32_t val[ITEMS];
     uint32_t rnk[ITEMS];
+    // all loads of the tile first, so that they are in flight together (a
+    // conversion next to each load made every load wait for the one before)
+    using In = typename std::conditional<FIRST, V, K>::type;
+    In in[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        in[i] = idx < T.n ? ((const In *)src)[T.base + idx] : (In)0;
+        val[i] = 0;
+        if constexpr (PAYLOAD && !FIRST)
+            if (idx < T.n) val[i] = vals_in[T.base + idx];
+    }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = t0 + i * 64 + lane;
         key[i] = 0;
-        val[i] = 0;
         if (idx < T.n) {
             if constexpr (FIRST) {
-                key[i] = key_of(((const V *)src)[T.base + idx]);
+                key[i] = key_of(in[i]);
                 val[i] = (uint32_t)idx;
             } else {
-                key[i] = ((const K *)src)[T.base + idx];
-                if constexpr (PAYLOAD) val[i] = vals_in[T.base + idx];
+                key[i] = in[i];
             }
         }
     }
@@ -432,10 +442,20 @@ rs_fixup(const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ vals
     const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const uint64_t *k = keys_in + T.base;
     const int64_t n = T.n, t0 = (int64_t)T.blk * TILE;
-    // sk[j] = k[t0 - FIX_HALO + j] where that position exists
-    for (int j = threadIdx.x; j < TILE + 2 * FIX_HALO; j += RS_THREADS) {
+    // sk[j] = k[t0 - FIX_HALO + j] where that position exists; all loads
+    // first, so that they are in flight together
+    constexpr int SK = TILE + 2 * FIX_HALO, SK_PER = (SK + RS_THREADS - 1) / RS_THREADS;
+    uint64_t ld[SK_PER];
+#pragma unroll
+    for (int r = 0; r < SK_PER; ++r) {
+        const int j = (int)threadIdx.x + r * RS_THREADS;
         const int64_t q = t0 - FIX_HALO + j;
-        sk[j] = (q >= 0 && q < n) ? k[q] : 0ull;
+        ld[r] = (j < SK && q >= 0 && q < n) ? k[q] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < SK_PER; ++r) {
+        const int j = (int)threadIdx.x + r * RS_THREADS;
+        if (j < SK) sk[j] = ld[r];
     }
     __syncthreads();
     bool too_long = false;
