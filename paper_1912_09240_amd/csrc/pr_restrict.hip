@@ -770,28 +770,26 @@ __global__ void __launch_bounds__(256) mk_extremes(MkArgs A) {
     const K *sorted = (const K *)A.sorted + R.base;
     const int64_t n = R.n;
     const double nd = (double)n, Q = (double)A.nq;
-#pragma unroll 1
+    // all sixteen loads of a thread first, so that they are in flight together
+    K v[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t e0 = g * (MK_GROUP * 64) + w * 1024 + i * 256 + 4 * lane;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[i][t] = e0 + t < n ? sorted[e0 + t] : (K)0;
+    }
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
         // ranks e0..e0+3 of chunk 16 w + 4 i + lane / 16 of the group
         const int64_t e0 = g * (MK_GROUP * 64) + w * 1024 + i * 256 + 4 * lane;
         K kx = 0, kn = ~(K)0;
-        K v[4];
-        if (e0 + 4 <= n) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) v[t] = sorted[e0 + t];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const K z = matched_key<K>(v[t], e0 + t, dk, nd, Q);
+        for (int t = 0; t < 4; ++t) {
+            if (e0 + t < n) {
+                const K z = matched_key<K>(v[i][t], e0 + t, dk, nd, Q);
                 kx = z > kx ? z : kx;
                 kn = z < kn ? z : kn;
             }
-        } else {
-            for (int t = 0; t < 4; ++t)
-                if (e0 + t < n) {
-                    const K z = matched_key<K>(sorted[e0 + t], e0 + t, dk, nd, Q);
-                    kx = z > kx ? z : kx;
-                    kn = z < kn ? z : kn;
-                }
         }
         for (int off = 1; off < 16; off <<= 1) {  // over the 16 lanes of the chunk
             const K ox = (K)__shfl_xor((unsigned long long)kx, off), on = (K)__shfl_xor((unsigned long long)kn, off);
