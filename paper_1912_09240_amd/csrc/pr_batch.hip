@@ -138,8 +138,7 @@ __global__ void __launch_bounds__(256) k2m_units(const double *__restrict__ q, c
 
 // E rho for 4 rows of one unit per block, one wave per row.
 __device__ __forceinline__ double row_dot(const double *row, const double *v, int n, int lane) {
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc = fma(row[j], v[j], acc);
+    double acc = lane_row_dot(row, v, n, lane);
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     return acc;
 }

@@ -124,8 +124,7 @@ __global__ void __launch_bounds__(256) apply_expm_knots(const double *__restrict
     const int r = blockIdx.x * 4 + wave;
     if (r >= n) return;
     const double *row = Es + (int64_t)r * n;
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc = fma(row[j], rv[j], acc);
+    double acc = lane_row_dot(row, rv, n, lane);
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) rout[r] = acc > 0.0 ? acc : 0.0;
 }
@@ -143,8 +142,7 @@ __global__ void __launch_bounds__(256) apply_expm(const double *__restrict__ E, 
     const int r = blockIdx.x * 4 + wave;
     if (r >= n) return;
     const double *row = Es + (int64_t)r * n;
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc = fma(row[j], rv[j], acc);
+    double acc = lane_row_dot(row, rv, n, lane);
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) rout[(int64_t)s * n + r] = acc > 0.0 ? acc : 0.0;
 }

@@ -8,6 +8,23 @@
 
 namespace pr {
 
+// One lane's share of a row-vector product (elements lane, lane + 64, ...):
+// the loads of the row run eight ahead of the multiply-adds, whose order stays
+// the element order, so the sum is that of the plain loop.
+__device__ __forceinline__ double lane_row_dot(const double *__restrict__ row, const double *v, int n, int lane) {
+    double acc = 0.0;
+    int j = lane;
+    for (; j + 7 * 64 < n; j += 8 * 64) {
+        double e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = row[j + u * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(e[u], v[j + u * 64], acc);
+    }
+    for (; j < n; j += 64) acc = fma(row[j], v[j], acc);
+    return acc;
+}
+
 // ---------------------------------------------------------------------------
 // Knots -> cell masses (H).  c(x) = 0 for x <= q_0, 1 for x > q_Q, else
 // (j + (x - q_j)/(q_{j+1} - q_j))/Q with j the largest index with q_j < x
