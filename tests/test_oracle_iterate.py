@@ -3,6 +3,7 @@ monotone repair (Sec. 4.4), fast-marginal matching (Sec. 5.1) with its
 projection property (eq. (projection)), the generic iteration against the
 closed form of classical parareal for a linear scalar problem (Sec. 3.1),
 and the exactness property of the micro-macro iteration (Sec. 3.3.3)."""
+import math
 from math import comb
 
 import numpy as np
@@ -150,3 +151,17 @@ def test_schedule():
     assert b[0] == 0 and b[-1] == S and set(np.diff(b)) == {1562, 1563}
     S, dt = I.total_steps(2.0, 0.0123 / 20)
     assert S == round(2.0 / (0.0123 / 20)) and abs(S * dt - 2.0) < 1e-12
+
+
+def test_quantile_error_hand_values():
+    """The RMS over all Q + 1 knots (Sec. 6's error measure taken on the
+    knots): one knot off by 3 among four gives sqrt(9/4) = 1.5 exactly (a mean
+    over Q = 3 would give sqrt(3)); a constant offset c gives |c|; the order
+    of the arguments does not matter."""
+    q = np.array([0.0, 1.0, 2.0, 3.0])
+    assert I.quantile_error(q + np.array([3.0, 0.0, 0.0, 0.0]), q) == 1.5
+    assert I.quantile_error(q - 0.25, q) == 0.25
+    a = np.array([0.5, -1.0, 2.0, 0.0, 4.0])
+    b = np.array([0.0, 1.0, 2.0, -2.0, 1.0])
+    # differences 0.5, -2, 0, 2, 3: squares sum to 17.25 over 5 knots
+    assert I.quantile_error(a, b) == I.quantile_error(b, a) == math.sqrt(17.25 / 5.0)

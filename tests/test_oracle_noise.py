@@ -225,3 +225,39 @@ def test_coupling_and_instance_params(oracle_lib):
         seen_n.add(n)
         seen_k.add(k)
     assert len(seen_n) == 7 and len(seen_k) > 40
+
+
+def test_instance_params_distributions(oracle_lib):
+    """The batched workload's draws over 4096 instances follow their laws:
+    log10 eps ~ U(-3, -1), lambda ~ U(0.5, 2) (Kolmogorov-Smirnov at the
+    0.1 % level), log2 P uniform on 12..18 and the slice count uniform on
+    8..64 (chi-square at the 0.1 % level), the four independent of each
+    other (rank correlations).  A slip in a range (10^(-3+u), 0.5 + u/2)
+    or in an integer draw (floor(6u), 8 + floor(56u)) fails one of them."""
+    n = 4096
+    d = np.array([P.instance_params(0, i) for i in range(n)], dtype=np.float64)
+    le, lam, lg, k = np.log10(d[:, 0]), d[:, 1], np.log2(d[:, 2]), d[:, 3]
+    assert st.kstest(le, st.uniform(loc=-3.0, scale=2.0).cdf).pvalue > 1e-3
+    assert st.kstest(lam, st.uniform(loc=0.5, scale=1.5).cdf).pvalue > 1e-3
+    assert le.min() > -3.0 and le.max() < -1.0 and lam.min() > 0.5 and lam.max() < 2.0
+    assert np.array_equal(lg, np.round(lg))
+    cnt = np.array([(lg == e).sum() for e in range(12, 19)])
+    assert cnt.sum() == n and st.chisquare(cnt).pvalue > 1e-3
+    cnt = np.array([(k == v).sum() for v in range(8, 65)])
+    assert cnt.sum() == n and st.chisquare(cnt).pvalue > 1e-3
+    cols = [le, lam, lg, k]
+    for a in range(4):
+        for b in range(a + 1, 4):
+            assert abs(st.spearmanr(cols[a], cols[b]).statistic) < 5.0 / np.sqrt(n)
+
+
+def test_coupling_distribution(oracle_lib):
+    """a_i ~ U(0.5, 1.5) over 4096 coefficients (Kolmogorov-Smirnov at the
+    0.1 % level; a slip to 0.5 + u/2 or to 1 + u fails it), and the
+    coefficients of one seed do not depend on how many are drawn."""
+    a = P.coupling(0, 0, 4096)
+    assert st.kstest(a, st.uniform(loc=0.5, scale=1.0).cdf).pvalue > 1e-3
+    assert a.min() >= 0.5 and a.max() < 1.5
+    assert np.array_equal(P.coupling(0, 0, 32), a[:32])
+    b = P.coupling(1, 0, 4096)
+    assert abs(st.spearmanr(a, b).statistic) < 5.0 / np.sqrt(4096)

@@ -100,3 +100,54 @@ def test_histogram_brute_force():
         ref[min(max(c, 0), I - 1)] += 1
     assert np.array_equal(h, ref)
     assert h.sum() == len(x)
+
+
+def test_hazen_at_equals_the_knots_at_their_levels():
+    """The single-level quantile of the observables at p = j/Q is the knot j
+    of the same sample (Sec. 4.4 rules), ends included: bit for bit where
+    j/Q is exact in binary (Q a power of two), else within the rounding of
+    the level p = j/Q (N eps in the position times the local gap)."""
+    rng = np.random.default_rng(3)
+    for N in (1, 2, 5, 64, 1001):
+        xs = np.sort(rng.standard_normal(N))
+        gap = np.diff(xs).max() if N > 1 else 0.0
+        for Q in (1, 4, 10, 64, 100, 128):
+            q = R.hazen_knots(xs, Q)
+            exact = Q & (Q - 1) == 0
+            for j in range(Q + 1):
+                v = R.hazen_at(xs, j / Q)[0]
+                if exact:
+                    assert v == q[j], (N, Q, j)
+                else:
+                    assert abs(v - q[j]) <= 2 * np.spacing(np.abs(xs).max()) + N * 2.3e-16 * gap, (N, Q, j)
+
+
+def test_hazen_at_matches_numpy_at_arbitrary_levels():
+    """numpy's own midpoint quantile at levels that are not knot levels,
+    the clamped ends and the interpolation position returned with it."""
+    rng = np.random.default_rng(4)
+    for N in (1, 2, 3, 17, 500, 4097):
+        x = rng.standard_normal(N) * 2.0
+        xs = np.sort(x)
+        gap = np.diff(xs).max() if N > 1 else 0.0
+        for p in np.concatenate([[0.0, 1.0, 0.5 / N, 1.0 - 0.5 / N], rng.random(40)]):
+            v, r, f = R.hazen_at(xs, float(p))
+            ref = np.quantile(x, p, method="hazen")
+            tol = 4 * np.spacing(np.abs(x).max()) + N * 2.3e-16 * gap
+            assert abs(v - ref) <= tol, (N, p)
+            t = p * N - 0.5
+            if t <= 0.0:
+                assert (v, r, f) == (xs[0], 0, 0.0)
+            elif t >= N - 1:
+                assert (v, r, f) == (xs[-1], N - 1, 0.0)
+            else:
+                assert r == math.floor(t) and 0.0 <= f < 1.0 and xs[r] <= v <= xs[r + 1]
+
+
+def test_hazen_at_worked_example():
+    xs = np.array([0.0, 1.0, 2.0, 4.0])  # t = 4p - 1/2
+    assert R.hazen_at(xs, 0.1)[0] == 0.0          # t = -0.1: the minimum
+    assert R.hazen_at(xs, 0.5)[0] == 1.5          # t = 1.5: midpoint of 1 and 2
+    assert R.hazen_at(xs, 0.75)[0] == 3.0         # t = 2.5: midpoint of 2 and 4
+    assert R.hazen_at(xs, 0.8125)[0] == 3.5       # t = 2.75: three quarters from 2 to 4
+    assert R.hazen_at(xs, 0.95)[0] == 4.0         # t = 3.3: the maximum
