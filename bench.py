@@ -48,6 +48,14 @@ VALU_OPS_PER_STEP = 79
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12  # B/s
+# FP64 vector peak of MI355X (256 CUs x 128 FP64 flop per clock x 2.4 GHz)
+FP64_PEAK = 78.6e12
+# FP64 flops of the Euler-Maruyama update of one particle-step (d = 1),
+# eq. (EMx)/(EMy) with dt folded into the coefficients: slow part 11
+# (d = x - y, x^2, (-dt c3) x^2 and four fused multiply-adds of two flops:
+# the cubic, linear and coupling terms and the noise), fast part 4 (two fused
+# multiply-adds, d shared).  The normals' own arithmetic is not counted.
+FP64_FLOP_PER_STEP = 15
 
 # HBM bytes of one launch of the fine kernel (all 64 slices) from two
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
@@ -74,6 +82,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192, help="particles in the oracle's sample")
     ap.add_argument("--flags", type=int, default=0, help="parareal flags (1 reuse coarse, 2 skip converged)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full measurements (empty: none)")
     return ap.parse_args()
 
 
@@ -175,7 +185,7 @@ def adjoint_measure(torch, pr):
                          "checkpoints every 256 steps, observables mean X_T^2 and quantiles 0.1/0.5/0.9, "
                          "4x4 Jacobian w.r.t. (lambda, eps, beta, c3) in one reverse sweep",
                 fwd_plus_adjoint_particle_steps_per_s=n * S / total, forward_ckpt_s=t_fwd, observables_s=t_obs,
-                reverse_s=t_adj, plain_forward_s=t_plain,
+                reverse_s=t_adj, plain_forward_s=t_plain, reverse_over_forward=t_adj / t_fwd,
                 ratio_to_8_crn_fd_forwards=total / (8 * t_plain),
                 jacobian=jac.cpu().tolist(), observables=obs.cpu().tolist())
 
@@ -187,10 +197,12 @@ def batched_measure(torch, pr):
     """Batched form: 256 instances of the 2-D SDE with eps log-uniform in
     [1e-3, 1e-1], lambda ~ U(0.5, 2), P in {2^12..2^18}, N in {8..64} slices,
     dt = eps/20, T = 2 (drawn from the seed), coarse grid 200 cells, 100
-    levels.  The same handle runs iterations in the three launch patterns,
-    which produce the same bits (so the same quantile error): per-instance
-    launches, batched launches, and the batched iteration replayed as a
-    hipGraph.  Device time per iteration from HIP events."""
+    levels.  Two handles of the same batch run the same number of
+    iterations: one as batched launches and hipGraph replays, the other
+    instance by instance (the plain launch pattern).  Their knots of every
+    state of every instance are then compared bit for bit, so the sweep times
+    are compared at the same quantile error.  Device time per iteration from
+    HIP events."""
     b = BATCH
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
     with torch.cuda.stream(stream):
@@ -204,18 +216,37 @@ def batched_measure(torch, pr):
             sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=b["beta"]))
             scheds.append(pr.Schedule(S, int(K), b["T"] / S))
             ns.append(2 ** int(lg))
+        grid = pr.Grid(n_cells=b["cells"], n_q=b["nq"])
+        rows = sum(sc.n_slices + 1 for sc in scheds)
+
+        def knots(h):
+            out = torch.empty((rows, b["nq"] + 1), dtype=torch.float64, device="cuda")
+            r = 0
+            for i, sc in enumerate(scheds):
+                for t in range(sc.n_slices + 1):
+                    pr.pr_parareal_batch_state(h, i, t, q=out[r])
+                    r += 1
+            return out
+
         t0 = time.perf_counter()
-        h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=b["cells"], n_q=b["nq"]), b["seed"],
-                                        flags=pr.PR_AUTOTUNE)
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, b["seed"], flags=pr.PR_AUTOTUNE)
         t_create = time.perf_counter() - t0
         try:
             info = pr.pr_parareal_batch_info(h)
             pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_GRAPH)  # capture + warm-up
             ms_graph = pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH, timed=True) / 2
             ms_batched = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED, timed=True)
-            ms_plain = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_PER_INSTANCE, timed=True)
+            qa = knots(h)
         finally:
             pr.pr_parareal_batch_destroy(h)
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, b["seed"], flags=pr.PR_AUTOTUNE)
+        try:
+            pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_PER_INSTANCE)
+            ms_plain = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_PER_INSTANCE, timed=True)
+            qb = knots(h)
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+        same = bool(torch.equal(qa, qb))
     w = info["particle_steps"]
     return dict(workload="256 instances of the 2-D SDE, eps log-uniform [1e-3, 1e-1], lambda U(0.5, 2), "
                          "P in 2^12..2^18, N in 8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels",
@@ -225,7 +256,7 @@ def batched_measure(torch, pr):
                 particle_steps_per_s_graph=w / (ms_graph / 1e3),
                 particle_steps_per_s_per_instance=w / (ms_plain / 1e3),
                 speedup_vs_per_instance=ms_plain / ms_graph, create_s=t_create,
-                same_quantile_error="the three launch patterns give bitwise identical states (tested)")
+                same_quantile_error=same, iterations_compared=4)
 
 
 HIGHDIM = dict(d=32, n=2 ** 20, dt=1e-4, T=5.0, K=32, eps=0.01, beta=2.0, lam=1.0, seed=0)
@@ -550,36 +581,84 @@ def main():
         t = phases[name] * 1e-3
         hbm_phases[name] = dict(bytes=b, ms=phases[name], achieved_gbs=b / t / 1e9, frac=b / t / HBM_PEAK)
 
-    out = dict(metric=METRIC, value=value, unit="particle-steps/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload="slow-fast SDE, eps=0.01, P=2^20 FP64 particles, dt=1e-4, T=10 "
-                                    "(1e5 steps), 64 slices, 1024-cell coarse grid, 100 quantile levels, "
-                                    "one parareal iteration per step", particles=n, fine_steps=S, slices=K,
-                           cells=w["cells"], quantile_levels=nq, flags=args.flags, seed=w["seed"]),
-               roofline=roofline,
-               sweep_roofline=sweep_roofline,
-               hbm_phases=hbm_phases,
-               phases_ms=phases,
-               quantile_error=dict(at_T=[float(errs[2 * i]) for i in range(args.warmup + args.steps)],
-                                   max_over_slices=[float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]),
-               serial_fine_s=t_serial, create_s=t_create)
+    qerr_T = [float(errs[2 * i]) for i in range(args.warmup + args.steps)]
+    qerr_max = [float(errs[2 * i + 1]) for i in range(args.warmup + args.steps)]
+    config = dict(workload="slow-fast SDE, eps=0.01, P=2^20 FP64 particles, dt=1e-4, T=10 (1e5 steps), 64 slices, "
+                           "1024-cell coarse grid, 100 quantile levels, one parareal iteration per step",
+                  particles=n, fine_steps=S, slices=K, cells=w["cells"], quantile_levels=nq, flags=args.flags,
+                  seed=w["seed"])
+    detail = dict(metric=METRIC, value=value, unit="particle-steps/s", steps=args.steps, warmup=args.warmup,
+                  ms_per_step=ms_step, config=config, roofline=roofline, sweep_roofline=sweep_roofline,
+                  hbm_phases=hbm_phases, phases_ms=phases,
+                  quantile_error=dict(at_T=qerr_T, max_over_slices=qerr_max),
+                  serial_fine_s=t_serial, create_s=t_create)
     log("adjoint")
-    out["adjoint"] = adjoint_measure(torch, pr)
+    detail["adjoint"] = adjoint_measure(torch, pr)
     log("batched instances")
-    out["batched"] = batched_measure(torch, pr)
+    detail["batched"] = batched_measure(torch, pr)
     log("fast part in R^32")
-    out["high_dim"] = highdim_measure(torch, pr)
+    detail["high_dim"] = highdim_measure(torch, pr)
     log("histogram states")
-    out["hist_states"] = hist_measure(torch, pr, w, n, K, S, dt)
+    detail["hist_states"] = hist_measure(torch, pr, w, n, K, S, dt)
     log("chemical-reaction workload")
-    out["chemical"] = chem_measure(torch, pr)
+    detail["chemical"] = chem_measure(torch, pr)
     log("linear advection")
-    out["advection"] = advection_measure(torch, pr)
+    detail["advection"] = advection_measure(torch, pr)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
-    print(json.dumps(out), flush=True)
+        detail["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    if args.detail:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(detail, f, indent=1)
+    line = summary_line(detail, args, config)
+    text = json.dumps(line, separators=(",", ":"))
+    assert len(text) <= 4096, f"summary line of {len(text)} bytes"
+    print(text, flush=True)
+
+
+def _sig(v, digits=4):
+    return None if v is None else float(f"{v:.{digits}g}")
+
+
+def summary_line(d, args, config):
+    """The one JSON line of the run: the large workload's iteration rate with
+    its roofline, the CPU baseline, and short summaries of the differentiated
+    and batched forms (the full measurements are in the detail file)."""
+    r = d["roofline"]
+    line = dict(metric=d["metric"], value=_sig(d["value"], 6), unit=d["unit"], n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=_sig(d["ms_per_step"], 6), higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic (Philox-seeded, seed 0)",
+                config=dict(workload=config["workload"], particles=config["particles"],
+                            fine_steps=config["fine_steps"], slices=config["slices"], cells=config["cells"],
+                            quantile_levels=config["quantile_levels"], flags=config["flags"]))
+    line["roofline"] = dict(bound=r["bound"], achieved=_sig(r["achieved"]), peak=_sig(r["peak"]), unit=r["unit"],
+                            frac=_sig(r["frac"]), traffic=r["traffic"], kernel=r["kernel"],
+                            ops_per_particle_step=r["ops_per_particle_step"], fine_ms=_sig(r["fine_ms"]),
+                            fp64_flop_per_particle_step=FP64_FLOP_PER_STEP,
+                            fp64_tflops=_sig(FP64_FLOP_PER_STEP * r["fine_particle_steps_per_s"] / 1e12),
+                            fp64_flop_frac=_sig(FP64_FLOP_PER_STEP * r["fine_particle_steps_per_s"] / FP64_PEAK))
+    cb = d.get("cpu_baseline")
+    if cb:
+        line["cpu_baseline"] = dict(value=_sig(cb["value"]), unit=cb["unit"], cores=cb["cores"], kind=cb["kind"],
+                                    sample=cb["sample"], cpu_model=cb.get("cpu_model"),
+                                    one_thread_value=_sig(cb.get("one_thread", {}).get("value")))
+    a = d["adjoint"]
+    line["adjoint"] = {k: (_sig(v) if isinstance(v, float) else v) for k, v in a.items()
+                       if k not in ("workload", "jacobian", "observables")}
+    b = d["batched"]
+    line["batched"] = dict(sweep_ms_graph=_sig(b["sweep_ms_graph"]), sweep_ms_batched=_sig(b["sweep_ms_batched"]),
+                           sweep_ms_per_instance=_sig(b["sweep_ms_per_instance"]),
+                           speedup_vs_per_instance=_sig(b["speedup_vs_per_instance"]),
+                           particle_steps_per_s_graph=_sig(b["particle_steps_per_s_graph"]),
+                           same_quantile_error=b["same_quantile_error"], iterations_compared=b["iterations_compared"])
+    line["sweep_roofline"] = dict(floor_ms=_sig(d["sweep_roofline"]["floor_ms"]),
+                                  frac=_sig(d["sweep_roofline"]["frac"]))
+    line["hbm_phases"] = {k: dict(ms=_sig(v["ms"]), frac=_sig(v["frac"])) for k, v in d["hbm_phases"].items()}
+    line["quantile_error_at_T"] = [_sig(e, 3) for e in d["quantile_error"]["at_T"]]
+    line["serial_fine_s"] = _sig(d["serial_fine_s"])
+    line["detail"] = args.detail
+    return line
 
 
 if __name__ == "__main__":

@@ -229,6 +229,22 @@ int pr_coarse_matrix(const void *coarse, int slice, const double **E);
 int pr_coarse_destroy(void *coarse);
 
 /*
+ * Quantile iterator J alone (Sec. 4.4, eq. (quantile_reconstruction)) on k
+ * independent rows of n_q+1 knots at the levels p_j = j/Q: for every row s
+ *   q_out[s] = PAVA(q_f[s] + (q_c_next[s] - q_c_star[s]))
+ * evaluated in the order shown, so that J(a, f, a) = f bit for bit
+ * (eq. (iterator_property)), then made non-decreasing by the monotone repair
+ * of Sec. 4.4 (crossing quantiles replaced by their average), read as
+ * pool-adjacent-violators with equal weights whose pool sums accumulate in
+ * the order of the serial stack form.  This is one link of the serial chain
+ * of pr_parareal_iterate without its coarse step (q_c_next = C_n(q^n)).
+ * Arrays: device, [k][n_q+1]; q_out may alias an input row for row.
+ * 1 <= n_q <= 2047.  k = 0 launches nothing.
+ */
+int pr_quantile_jump(const double *q_c_next, const double *q_f, const double *q_c_star, int k, int n_q,
+                     double *q_out, void *stream);
+
+/*
  * Micro-macro parareal (Sec. 3.2.3-3.2.4) with the quantile iterator
  * (Sec. 4.4, eq. (quantile_reconstruction); PAVA monotone repair) and
  * fast-marginal matching.  pr_parareal_create draws the initial ensemble and

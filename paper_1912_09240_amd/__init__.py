@@ -14,7 +14,7 @@ __all__ = [
     "Sde", "Schedule", "Grid", "PrError", "lib", "available",
     "pr_version", "pr_last_error", "pr_draw_coupling", "pr_init_ensemble", "pr_fine_propagate",
     "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles", "pr_match_knots",
-    "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy",
+    "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy", "pr_quantile_jump",
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
     "pr_parareal_knot_sorts", "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE",
     "PR_SKIP_CONVERGED", "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
@@ -142,6 +142,7 @@ _SIGS = {
     "pr_coarse_fp_step": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
     "pr_coarse_matrix": (_c_int, [_vp, _c_int, ctypes.POINTER(_vp)]),
     "pr_coarse_destroy": (_c_int, [_vp]),
+    "pr_quantile_jump": (_c_int, [_vp, _vp, _vp, _c_int, _c_int, _vp, _vp]),
     "pr_parareal_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid),
                                     _c_u64, _c_u32, _c_i64, _c_int, _vp, ctypes.POINTER(_vp)]),
     "pr_parareal_iterate": (_c_int, [_vp, _c_int, _vp, _vp, _vp]),
@@ -307,6 +308,10 @@ def pr_coarse_matrix(h, slice_index):
 
 def pr_coarse_destroy(h):
     _check(lib().pr_coarse_destroy(h))
+
+
+def pr_quantile_jump(q_c_next, q_f, q_c_star, k, n_q, q_out, stream=None):
+    _check(lib().pr_quantile_jump(_ptr(q_c_next), _ptr(q_f), _ptr(q_c_star), k, n_q, _ptr(q_out), _stream(stream)))
 
 
 def pr_parareal_create(sde, sched, grid, seed, instance, n, flags=0, stream=None):

@@ -7,13 +7,17 @@
 //
 // Memory plan: the forward pass stores the state every E steps (E = 256).
 // The reverse kernel walks every particle through the segments backwards.
-// For one segment it recomputes the E steps once, writing the state every 16
-// steps to a small global scratch; then for each 16-step sub-segment, last
-// first, it recomputes the 16 states into registers and runs the reverse
-// recursion over them.  The noise increments sx z0, sy z1 of a step are
-// recovered from two consecutive states, so the reverse sweep needs no
-// random numbers.  Up to four seed vectors (observables) are carried at once,
-// giving up to four rows of the Jacobian in one sweep.
+// For one segment it recomputes the E steps once, writing the state every
+// AD_SUB = 8 steps to a small global scratch; then for each 8-step
+// sub-segment, last first, it recomputes the 8 states into registers and
+// runs the reverse recursion over them.  Every recomputed step is the fine
+// propagator's own Euler-Maruyama step (em_step), so the checkpoints and the
+// replayed states carry the bits of pr_fine_propagate.  The noise increments
+// sx z0, sy z1 of a step are recovered from two consecutive states, so the
+// reverse recursion itself needs no random numbers.  Up to four seed vectors
+// (observables) are carried at once, giving up to four rows of the Jacobian
+// in one sweep.
+#include "pr_fine_dev.hpp"
 #include "pr_internal.hpp"
 
 namespace pr {
@@ -25,20 +29,19 @@ struct AdCoef {
     double c3, c1, lam, dt, rate, sx, sy, beta, eps;
 };
 
-__device__ __forceinline__ void em_step_d1(double &x, double &y, const AdCoef &c, const NoiseTab &tab, Key key,
-                                           uint32_t inst, uint32_t m, uint32_t p) {
-    double z0, z1;
-    box_muller(noise_block(key, inst, 0u, m, p, 0u), tab, z0, z1);
-    const double fx = c.c3 * x * x * x + c.c1 * x + c.lam * (x - y);
-    const double xn = x - c.dt * fx + c.sx * z0;
-    y = y - c.rate * (y - x) + c.sy * z1;
-    x = xn;
+// One step of the fine propagator (eq. (EMx)/(EMy), d = 1, FP64).
+__device__ __forceinline__ void em_step_d1(double &x, double &y, const EmCoef<double> &ec, const NoiseTab &tab,
+                                           Key key, uint32_t inst, uint32_t m, uint32_t p) {
+    const double a1[1] = {1.0};
+    double yv[1] = {y};
+    em_step<1, double>(x, yv, a1, ec, tab, key, inst, m, p);
+    y = yv[0];
 }
 
 // Forward over all steps [0, S) of one segment in time, with checkpoints.
 __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, double *__restrict__ y, int64_t n,
-                                                       int64_t S, int every, double *__restrict__ ckpt, AdCoef c,
-                                                       Key key, uint32_t inst) {
+                                                       int64_t S, int every, double *__restrict__ ckpt,
+                                                       EmCoef<double> ec, Key key, uint32_t inst) {
     __shared__ NoiseTab tab;
     load_noise_tab(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,7 +52,7 @@ __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, d
         ckpt[(cidx * 2) * n + p] = xv;
         ckpt[(cidx * 2 + 1) * n + p] = yv;
         const int64_t m1 = m0 + every < S ? m0 + every : S;
-        for (int64_t m = m0; m < m1; ++m) em_step_d1(xv, yv, c, tab, key, inst, (uint32_t)m, (uint32_t)p);
+        for (int64_t m = m0; m < m1; ++m) em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
     }
     x[p] = xv;
     y[p] = yv;
@@ -59,7 +62,8 @@ template <int NS>
 __global__ void __launch_bounds__(AD_THREADS)
 adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n, int64_t S,
                const double *__restrict__ seed_x, const double *__restrict__ seed_y, int from_initial,
-               double *__restrict__ sub, double *__restrict__ part, AdCoef c, Key key, uint32_t inst) {
+               double *__restrict__ sub, double *__restrict__ part, AdCoef c, EmCoef<double> ec, Key key,
+               uint32_t inst) {
     __shared__ NoiseTab tab;
     load_noise_tab(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,7 +89,7 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
                 sub[(2 * (int64_t)nsub) * n + p] = xv;
                 sub[(2 * (int64_t)nsub + 1) * n + p] = yv;
                 const int64_t me = ms + AD_SUB < m1 ? ms + AD_SUB : m1;
-                for (int64_t m = ms; m < me; ++m) em_step_d1(xv, yv, c, tab, key, inst, (uint32_t)m, (uint32_t)p);
+                for (int64_t m = ms; m < me; ++m) em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
             }
             // level 2: each sub-segment, last first
             for (int j = nsub - 1; j >= 0; --j) {
@@ -97,7 +101,7 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
 #pragma unroll
                 for (int i = 0; i < AD_SUB; ++i) {
                     double a = tx[i], b = ty[i];
-                    if (i < L) em_step_d1(a, b, c, tab, key, inst, (uint32_t)(ms + i), (uint32_t)p);
+                    if (i < L) em_step_d1(a, b, ec, tab, key, inst, (uint32_t)(ms + i), (uint32_t)p);
                     tx[i + 1] = a;
                     ty[i + 1] = b;
                 }
@@ -292,7 +296,7 @@ extern "C" int pr_fine_checkpoint(const pr_sde *sde, const pr_schedule *sched, u
     PR_REQUIRE(x && y && ckpt, "x, y and ckpt must be non-NULL");
     hipLaunchKernelGGL(fwd_ckpt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream),
                        (double *)x, (double *)y, n, sched->total_steps, ckpt_every, ckpt,
-                       make_adcoef(sde, sched->dt), make_key(seed), instance);
+                       make_coef<double>(sde, sched->dt), make_key(seed), instance);
     PR_LAUNCHED();
     return PR_OK;
 }
@@ -325,19 +329,20 @@ extern "C" int pr_fine_adjoint(const pr_sde *sde, const pr_schedule *sched, uint
     double *part = base + (size_t)2 * nsub * n;
     hipStream_t st = as_stream(stream);
     const AdCoef c = make_adcoef(sde, sched->dt);
+    const EmCoef<double> ec = make_coef<double>(sde, sched->dt);
     const dim3 grid((unsigned)nblk);
     switch (n_seed) {
         case 1: hipLaunchKernelGGL(adjoint_kernel<1>, grid, dim3(AD_THREADS), 0, st, ckpt, nck, ckpt_every, n,
-                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, make_key(seed),
+                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, ec, make_key(seed),
                                    instance); break;
         case 2: hipLaunchKernelGGL(adjoint_kernel<2>, grid, dim3(AD_THREADS), 0, st, ckpt, nck, ckpt_every, n,
-                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, make_key(seed),
+                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, ec, make_key(seed),
                                    instance); break;
         case 3: hipLaunchKernelGGL(adjoint_kernel<3>, grid, dim3(AD_THREADS), 0, st, ckpt, nck, ckpt_every, n,
-                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, make_key(seed),
+                                   sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, ec, make_key(seed),
                                    instance); break;
         default: hipLaunchKernelGGL(adjoint_kernel<4>, grid, dim3(AD_THREADS), 0, st, ckpt, nck, ckpt_every, n,
-                                    sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, make_key(seed),
+                                    sched->total_steps, seed_x, seed_y, from_initial, sub, part, c, ec, make_key(seed),
                                     instance); break;
     }
     PR_LAUNCHED();

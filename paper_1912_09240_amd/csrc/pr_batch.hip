@@ -244,6 +244,22 @@ __global__ void __launch_bounds__(256) match_batch_kernel(const MatchSeg *__rest
     }
 }
 
+// After the zeroth iteration: the time-0 state of every instance into the
+// other ping-pong buffer, and the fast variables of time 0 into every later
+// time point of buffer 0 (matching moves the slow variable only).  One
+// launch for the whole batch: blockIdx.y is the instance.
+__global__ void spread_time0(const InstDev *__restrict__ insts, double *__restrict__ x0, double *__restrict__ y0,
+                             double *__restrict__ x1, double *__restrict__ y1) {
+    const InstDev I = insts[blockIdx.y];
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < I.n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = I.xoff + p;
+        const double xv = x0[o], yv = y0[o];
+        x1[o] = xv;
+        y1[o] = yv;
+        for (int t = 1; t <= I.K; ++t) y0[o + (int64_t)t * I.n] = yv;
+    }
+}
+
 __global__ void copy_f64(const double *__restrict__ a, double *__restrict__ b, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         b[i] = a[i];
@@ -767,22 +783,24 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
         MatchArgs ma{b->q + (int64_t)(r0 + 1) * (b->Q + 1), b->Q + 1, b->q + (int64_t)r0 * (b->Q + 1), 0,
                      b->rank + xo_i, 0, b->x[0] + xo_i, 0, b->x[0] + xo_i + ni, ni};
         PR_CHECK(match_strided(ma, ni, K, b->Q, PR_F64, st));
-        for (int t = 1; t <= K; ++t) {
-            hipLaunchKernelGGL(copy_f64, dim3((unsigned)std::min<int64_t>((ni + 255) / 256, 1024)), dim3(256), 0, st,
-                               (const double *)(b->y[0] + xo_i), b->y[0] + xo_i + (int64_t)t * ni, ni);
-            PR_LAUNCHED();
-        }
-        for (int p = 0; p < 2; ++p) {
-            hipLaunchKernelGGL(copy_f64, dim3((unsigned)std::min<int64_t>((ni + 255) / 256, 1024)), dim3(256), 0, st,
-                               (const double *)(b->x[0] + xo_i), b->x[1] + xo_i, ni);
-            hipLaunchKernelGGL(copy_f64, dim3((unsigned)std::min<int64_t>((ni + 255) / 256, 1024)), dim3(256), 0, st,
-                               (const double *)(b->y[0] + xo_i), b->y[1] + xo_i, ni);
-            PR_LAUNCHED();
-        }
         PR_CHECK(restrict_quantiles(b->x[0] + xo_i, PR_F64, ni, K + 1, b->Q, nullptr,
                                     b->qR + (int64_t)r0 * (b->Q + 1), nullptr, nullptr, nullptr, nullptr, nullptr,
                                     b->ws, st));
     }
+    // every instance's states [xoff, xoff + (K+1) n) lie inside the buffers
+    // and do not overlap the next instance's
+    int64_t max_n = 1;
+    for (int i = 0; i < B; ++i) {
+        const int64_t end = b->xoff[i] + (int64_t)(sch[i].n_slices + 1) * n[i];
+        if (b->xoff[i] < 0 || end > xo || (i + 1 < B && end != b->xoff[i + 1])) {
+            set_error("state layout of instance %d out of bounds", i);
+            return PR_E_INVALID;
+        }
+        max_n = std::max(max_n, n[i]);
+    }
+    hipLaunchKernelGGL(spread_time0, dim3((unsigned)std::min<int64_t>((max_n + 255) / 256, 256), (unsigned)B),
+                       dim3(256), 0, st, (const InstDev *)b->inst, b->x[0], b->y[0], b->x[1], b->y[1]);
+    PR_LAUNCHED();
     PR_HIP(hipStreamSynchronize(st));
     if (flags & PR_AUTOTUNE) PR_CHECK(autotune(b, st));
     PR_CHECK(fine_slots(b->tuned, b->persist_blocks));

@@ -184,6 +184,25 @@ __global__ void __launch_bounds__(256) qf_and_jump(const double *__restrict__ rh
     for (int j = threadIdx.x; j <= g.nq; j += blockDim.x) q_out[j] = qc[j];
 }
 
+// The quantile iterator alone on k independent rows of L = Q + 1 knots:
+// q_out[s] = PAVA(q_f[s] + (q_c_next[s] - q_c_star[s])), the arithmetic and the
+// monotone repair of qf_and_jump.  One block per row; every row is read into
+// LDS before any write, so q_out may alias the inputs row for row.
+__global__ void __launch_bounds__(256) quantile_jump_rows(const double *__restrict__ qcn, const double *__restrict__ qf,
+                                                          const double *__restrict__ qcs, double *q_out, int L) {
+#pragma clang fp contract(off)
+    extern __shared__ double sh[];
+    double *qc = sh;
+    double *S = qc + L;
+    int *SC = (int *)(S + L);
+    int *vio = SC + L;
+    const int64_t o = (int64_t)blockIdx.x * L;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) qc[j] = qf[o + j] + (qcn[o + j] - qcs[o + j]);
+    __syncthreads();
+    pava_block(qc, L, S, SC, vio);
+    for (int j = threadIdx.x; j < L; j += blockDim.x) q_out[o + j] = qc[j];
+}
+
 // ---------------------------------------------------------------------------
 // Handle.
 // ---------------------------------------------------------------------------
@@ -454,5 +473,19 @@ extern "C" int pr_coarse_matrix(const void *coarse, int slice, const double **E)
 extern "C" int pr_coarse_destroy(void *coarse) {
     clear_error();
     coarse_free((Coarse *)coarse);
+    return PR_OK;
+}
+
+extern "C" int pr_quantile_jump(const double *q_c_next, const double *q_f, const double *q_c_star, int k, int n_q,
+                                double *q_out, void *stream) {
+    clear_error();
+    PR_REQUIRE(k >= 0, "k must be >= 0");
+    PR_REQUIRE(n_q >= 1 && n_q <= 2047, "n_q must be in [1, 2047]");
+    if (k == 0) return PR_OK;
+    PR_REQUIRE(q_c_next && q_f && q_c_star && q_out, "the knot arrays must be non-NULL");
+    const int L = n_q + 1;
+    hipLaunchKernelGGL(quantile_jump_rows, dim3((unsigned)k), dim3(256), (sizeof(double) * 2 + sizeof(int) * 2) * L,
+                       as_stream(stream), q_c_next, q_f, q_c_star, q_out, L);
+    PR_LAUNCHED();
     return PR_OK;
 }

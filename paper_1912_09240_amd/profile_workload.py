@@ -9,6 +9,10 @@ that rocprofv3 counter passes cover a handful of dispatches.
     python -m paper_1912_09240_amd.profile_workload hist      # histograms, marginal matching and
                                                               # stratified resampling, 64 x 2^20
     python -m paper_1912_09240_amd.profile_workload chem      # chemical-reaction fine launch (Table 1)
+    python -m paper_1912_09240_amd.profile_workload adjoint   # differentiated form: forward with
+                                                              # checkpoints, observables, reverse sweep
+    python -m paper_1912_09240_amd.profile_workload batch     # batched form: creation (zeroth iteration)
+                                                              # of 256 instances and one batched iteration
 
 Large workload: lambda = 1, beta = 2, eps = 0.01, P = 2^20, dt = 1e-4, T = 10
 (1e5 steps) in 64 slices, 100 quantile levels; the slice states start from
@@ -110,7 +114,56 @@ def chem():
         torch.cuda.synchronize()
 
 
+def adjoint():
+    """Differentiated form: P = 2^20, 1e4 steps of dt = 1e-4 (lambda = 1,
+    eps = 0.1, beta = 2), checkpoints every 256 steps, the four observables'
+    seed vectors, one reverse sweep for all four."""
+    n, s_total, dt, every = 2 ** 20, 10_000, 1e-4, 256
+    sde = pr.Sde(lam=1.0, eps=0.1, beta=2.0)
+    sched = pr.Schedule(s_total, 1, dt)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ck = torch.empty(((s_total + every - 1) // every, 2, n), dtype=torch.float64, device="cuda")
+    obs = torch.empty(4, dtype=torch.float64, device="cuda")
+    seeds = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    wso = torch.empty(pr.pr_observables_workspace_size(n), dtype=torch.uint8, device="cuda")
+    jac = torch.empty((4, 4), dtype=torch.float64, device="cuda")
+    wsa = torch.empty(pr.pr_adjoint_workspace_size(n, every, 4), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        pr.pr_init_ensemble(sde, 0, 0, n, x, y)
+        pr.pr_fine_checkpoint(sde, sched, 0, 0, n, x, y, ck, every)
+        pr.pr_observables(x, n, [0.1, 0.5, 0.9], obs, wso, seed_x=seeds)
+        pr.pr_fine_adjoint(sde, sched, 0, 0, n, ck, every, seeds, 4, jac, wsa)
+        torch.cuda.synchronize()
+
+
+def batch():
+    """Batched form as the benchmark runs it: 256 instances drawn from seed
+    0 (eps log-uniform in [1e-3, 1e-1], lambda in [0.5, 2], P in 2^12..2^18,
+    8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels); creation runs
+    the zeroth iteration, then one iteration in batched launches."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        draw = torch.empty((256, 4), dtype=torch.float64, device="cuda")
+        pr.pr_draw_instances(0, 256, draw)
+        sdes, scheds, ns = [], [], []
+        for eps, lam, lg, k in draw.cpu().numpy():
+            dt = eps / 20
+            s_total = int(round(2.0 / dt))
+            sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=2.0))
+            scheds.append(pr.Schedule(s_total, int(k), 2.0 / s_total))
+            ns.append(2 ** int(lg))
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=200, n_q=100), 0)
+        try:
+            print("batch: created", flush=True)
+            pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED)
+            torch.cuda.synchronize()
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+
+
 if __name__ == "__main__":
     group = sys.argv[1] if len(sys.argv) > 1 else "fine"
-    {"fine": fine, "restrict": restrict, "match": match, "copy": copy, "hist": hist, "chem": chem}[group]()
+    {"fine": fine, "restrict": restrict, "match": match, "copy": copy, "hist": hist, "chem": chem, "adjoint": adjoint,
+     "batch": batch}[group]()
     print(f"profile_workload {group}: done", flush=True)

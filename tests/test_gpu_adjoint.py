@@ -112,3 +112,65 @@ def test_autograd_binding(torch_dev):
     pr.pr_fine_adjoint(sde, sched, 0, 0, 8192, ck, 128, seeds, 4, jac, ws)
     assert torch.equal(obs.detach(), obs2)
     assert torch.allclose(gt, w @ jac, rtol=1e-12, atol=0)
+
+
+def test_checkpoint_forward_is_the_fine_propagator_bitwise(torch_dev):
+    """The checkpointed forward steps with the fine propagator's own
+    Euler-Maruyama step: every checkpoint and the final state equal
+    pr_fine_propagate over the same steps bit for bit (here the slices of a
+    schedule whose slice bounds are the checkpoint steps)."""
+    torch = torch_dev
+    n, every, nck = 5000, 64, 7
+    S = every * nck
+    _say(f"checkpoint forward vs fine propagate n={n} S={S}")
+    sde = pr.Sde(lam=1.0, eps=0.1, beta=2.0, c3=1.0)
+    dt = 1e-3
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, 5, 2, n, x, y)
+    x2, y2 = x.clone(), y.clone()
+    ck = torch.empty((nck, 2, n), dtype=torch.float64, device="cuda")
+    pr.pr_fine_checkpoint(sde, pr.Schedule(S, 1, dt), 5, 2, n, x, y, ck, every)
+    sched = pr.Schedule(S, nck, dt)
+    for s in range(nck):
+        assert torch.equal(ck[s, 0], x2) and torch.equal(ck[s, 1], y2), s
+        pr.pr_fine_propagate(sde, sched, 5, 2, n, s, 1, x2, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(x, x2) and torch.equal(y, y2)
+
+
+def test_adjoint_full_size_on_a_particle_subset(torch_dev):
+    """The differentiated form at its full size (P = 2^20, 1e4 steps of
+    1e-4, checkpoints every 256 steps, 40 segments) with four seed vectors
+    that are non-zero on particles 0..1023 only: the reverse sweep of the
+    whole ensemble equals the oracle's forward-mode tangents of those 1024
+    particles (counter-based noise makes the subset exact) to 1e-10
+    relative, the initial law's dependence on beta included."""
+    torch = torch_dev
+    n, S, dt, every, m = 2 ** 20, 10_000, 1e-4, 256, 1024
+    _say(f"adjoint full size n={n} S={S} subset={m}")
+    sde = pr.Sde(lam=1.0, eps=0.1, beta=2.0, c3=1.0)
+    sched = pr.Schedule(S, 1, dt)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, 0, 0, n, x, y)
+    ck = torch.empty(((S + every - 1) // every, 2, n), dtype=torch.float64, device="cuda")
+    pr.pr_fine_checkpoint(sde, sched, 0, 0, n, x, y, ck, every)
+    rng = np.random.default_rng(41)
+    sx = np.zeros((4, n))
+    sy = np.zeros((4, n))
+    sx[:, :m] = rng.normal(0.0, 1.0, (4, m))
+    sy[:, :m] = rng.normal(0.0, 1.0, (4, m))
+    sy[0, :m] = 0.0  # one seed on the slow variable alone
+    jac = torch.empty((4, 4), dtype=torch.float64, device="cuda")
+    ws = torch.empty(pr.pr_adjoint_workspace_size(n, every, 4), dtype=torch.uint8, device="cuda")
+    pr.pr_fine_adjoint(sde, sched, 0, 0, n, ck, every, torch.from_numpy(sx).cuda(), 4, jac, ws,
+                       seed_y=torch.from_numpy(sy).cuda())
+    torch.cuda.synchronize()
+    xo, yo, dx, dy = OP.em_tangent(OP.Sde(lam=1.0, eps=0.1, beta=2.0, c3=1.0), 0, 0, m, S, dt)
+    assert np.abs(x.cpu().numpy()[:m] - xo).max() < 1e-12
+    ref = sx[:, :m] @ dx.T + sy[:, :m] @ dy.T
+    got = jac.cpu().numpy()
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    assert np.all(scale > 0.0)
+    assert np.all(np.abs(got - ref) <= 1e-10 * scale), (got, ref)
