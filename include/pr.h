@@ -186,6 +186,25 @@ int pr_match_quantiles(const double *q_target, const double *q_prior, const uint
                        int precision, void *stream);
 
 /*
+ * pr_restrict_quantiles for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results, bit for bit, without ws and
+ * ws_bytes.  The workspace is a static device array of
+ * PR_STATIC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; its device address is looked up once per GPU.  The call
+ * allocates nothing.  Requests whose workspace (pr_restrict_workspace_size)
+ * exceeds the array return PR_E_NOMEM before anything is launched (64 MiB:
+ * about 2.7 million FP64 keys over all k ensembles).  Every call on one GPU
+ * shares its array, so calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller; the call clears what
+ * it needs cleared itself.
+ */
+#define PR_STATIC_SCRATCH_BYTES (64u << 20)
+int pr_restrict_quantiles_static(const void *x, int precision, int64_t n, int k, int n_q,
+                                 const pr_grid *hist_grid, double *q, uint32_t *rank, uint32_t *perm,
+                                 double *x_sorted, double *moments, uint32_t *hist, void *stream);
+
+/*
  * Knots (Sec. 4.4, midpoint convention) of the matched ensembles without
  * sorting them.  For the k ensembles X that pr_match_quantiles(q_target,
  * q_prior, rank, n, k, n_q, x_prior, ...) makes from the priors, q_out

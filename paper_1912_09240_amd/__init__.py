@@ -13,7 +13,8 @@ import os
 __all__ = [
     "Sde", "Schedule", "Grid", "PrError", "lib", "available",
     "pr_version", "pr_last_error", "pr_draw_coupling", "pr_init_ensemble", "pr_fine_propagate",
-    "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_match_quantiles", "pr_match_knots",
+    "pr_restrict_workspace_size", "pr_restrict_quantiles", "pr_restrict_quantiles_static", "PR_STATIC_SCRATCH_BYTES",
+    "pr_match_quantiles", "pr_match_knots",
     "pr_coarse_create", "pr_coarse_fp_step", "pr_coarse_matrix", "pr_coarse_destroy", "pr_quantile_jump",
     "pr_parareal_create", "pr_parareal_iterate", "pr_parareal_state", "pr_parareal_iteration",
     "pr_parareal_knot_sorts", "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE",
@@ -34,6 +35,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpr.so")
 
 PR_F64, PR_F32 = 64, 32
+PR_STATIC_SCRATCH_BYTES = 64 << 20
 PR_REUSE_COARSE, PR_SKIP_CONVERGED, PR_PROFILE, PR_AUTOTUNE = 1, 2, 4, 8
 PR_LAUNCH_BATCHED, PR_LAUNCH_GRAPH, PR_LAUNCH_PER_INSTANCE = 0, 1, 2
 PR_J_ADD, PR_J_MULT, PR_J_ROT, PR_J_QUANTILE = 0, 1, 2, 3
@@ -135,6 +137,8 @@ _SIGS = {
     "pr_restrict_workspace_size": (ctypes.c_size_t, [_c_i64, _c_int, _c_int]),
     "pr_restrict_quantiles": (_c_int, [_vp, _c_int, _c_i64, _c_int, _c_int, ctypes.POINTER(_CGrid), _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "pr_restrict_quantiles_static": (_c_int, [_vp, _c_int, _c_i64, _c_int, _c_int, ctypes.POINTER(_CGrid), _vp, _vp,
+                                              _vp, _vp, _vp, _vp, _vp]),
     "pr_match_quantiles": (_c_int, [_vp, _vp, _vp, _c_i64, _c_int, _c_int, _vp, _vp, _c_int, _vp]),
     "pr_match_knots": (_c_int, [_vp, _vp, _c_i64, _c_int, _c_int, _c_int, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     "pr_coarse_create": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), ctypes.POINTER(_CGrid), _vp,
@@ -274,6 +278,13 @@ def pr_restrict_quantiles(x, precision, n, k, n_q, q, ws, rank=None, perm=None, 
     nbytes = ws.numel() * ws.element_size()
     _check(lib().pr_restrict_quantiles(_ptr(x), precision, n, k, n_q, g, _ptr(q), _ptr(rank), _ptr(perm),
                                        _ptr(x_sorted), _ptr(moments), _ptr(hist), _ptr(ws), nbytes, _stream(stream)))
+
+
+def pr_restrict_quantiles_static(x, precision, n, k, n_q, q, rank=None, perm=None, x_sorted=None, moments=None,
+                                 hist=None, hist_grid=None, stream=None):
+    g = ctypes.byref(hist_grid.c()) if hist_grid is not None else None
+    _check(lib().pr_restrict_quantiles_static(_ptr(x), precision, n, k, n_q, g, _ptr(q), _ptr(rank), _ptr(perm),
+                                              _ptr(x_sorted), _ptr(moments), _ptr(hist), _stream(stream)))
 
 
 def pr_match_quantiles(q_target, q_prior, rank, n, k, n_q, x_prior, x_out, precision=PR_F64, stream=None):

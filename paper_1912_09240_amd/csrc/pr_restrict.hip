@@ -24,6 +24,7 @@
 // (the ranks through a staging buffer instead of stores to random addresses,
 // rs_rank_bucket and rs_rank_place); the complete sort follows, guarded by a
 // flag that the fix-up raises only for a run longer than it handles.
+#include <mutex>
 #include <type_traits>
 
 #include "pr_internal.hpp"
@@ -1272,6 +1273,66 @@ extern "C" int pr_restrict_quantiles(const void *x, int precision, int64_t n, in
         set_error("workspace too small: %zu < %zu bytes", ws_bytes, restrict_ws(n, k, precision));
         return PR_E_NOMEM;
     }
+    return restrict_quantiles(x, precision, n, k, n_q, hist_grid, q, rank, perm, x_sorted, moments, hist, ws,
+                              as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Restriction without allocation: the workspace is a file-scope device array
+// of PR_STATIC_SCRATCH_BYTES (one copy per GPU, held until the process ends).
+// Host code never passes the array's name to a kernel: its device address on
+// the current GPU is taken once per device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PR_STATIC_SCRATCH_BYTES];
+
+namespace pr {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(void **out) {
+    int dev = 0;
+    PR_HIP(hipGetDevice(&dev));
+    PR_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d outside the %d devices served", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            return PR_E_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PR_OK;
+}
+}  // namespace
+}  // namespace pr
+
+extern "C" int pr_restrict_quantiles_static(const void *x, int precision, int64_t n, int k, int n_q,
+                                            const pr_grid *hist_grid, double *q, uint32_t *rank, uint32_t *perm,
+                                            double *x_sorted, double *moments, uint32_t *hist, void *stream) {
+    clear_error();
+    PR_REQUIRE(valid_precision(precision), "precision must be 64 or 32");
+    PR_REQUIRE(n >= 1 && n <= 0xFFFFFFFFll, "n must be in [1, 2^32)");
+    PR_REQUIRE(k >= 1 && k <= 65535, "k must be in [1, 65535]");
+    PR_REQUIRE(n_q >= 1 && n_q <= 1 << 20, "n_q must be in [1, 2^20]");
+    PR_REQUIRE(x != nullptr && q != nullptr, "x and q must be non-NULL");
+    if (hist) {
+        PR_REQUIRE(hist_grid != nullptr, "hist requires hist_grid");
+        PR_REQUIRE(hist_grid->n_cells >= 1 && hist_grid->n_cells <= 8192 && hist_grid->x_lo < hist_grid->x_hi,
+                   "hist_grid must have 1..8192 cells and x_lo < x_hi");
+    }
+    const size_t need = restrict_ws(n, k, precision);
+    if (need > (size_t)PR_STATIC_SCRATCH_BYTES) {
+        set_error("n * k = %lld keys need %zu bytes of scratch; the static scratch holds %zu",
+                  (long long)n * k, need, (size_t)PR_STATIC_SCRATCH_BYTES);
+        return PR_E_NOMEM;
+    }
+    void *ws = nullptr;
+    PR_CHECK(scratch_on_current_device(&ws));
     return restrict_quantiles(x, precision, n, k, n_q, hist_grid, q, rank, perm, x_sorted, moments, hist, ws,
                               as_stream(stream));
 }

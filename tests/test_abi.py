@@ -99,6 +99,13 @@ def test_validation_rejects_before_launch(lib):
     assert L.pr_quantile_jump(p, p, p, 3, 2048, p, None) == -1
     assert L.pr_quantile_jump(None, p, p, 3, 100, p, None) == -1
     assert L.pr_quantile_jump(None, None, None, 0, 100, None, None) == 0
+    # the restriction without allocation: arguments and the size of the
+    # static scratch are checked before the device is touched
+    assert L.pr_restrict_quantiles_static(None, 64, 1000, 2, 100, None, p, None, None, None, None, None, None) == -1
+    assert L.pr_restrict_quantiles_static(p, 64, 1000, 2, 100, None, None, None, None, None, None, None, None) == -1
+    assert L.pr_restrict_quantiles_static(p, 16, 1000, 2, 100, None, p, None, None, None, None, None, None) == -1
+    assert L.pr_restrict_quantiles_static(p, 64, 1 << 20, 3, 100, None, p, None, None, None, None, None, None) == -3
+    assert "static scratch" in pr.pr_last_error()
     # iterate on a NULL handle
     assert L.pr_parareal_iterate(None, 1, None, None, None) == -1
 
