@@ -169,8 +169,14 @@ __global__ void __launch_bounds__(256) m2k_units(const double *__restrict__ rho,
 
 // Serial chain of one instance per block: q_{k+1}^{n+1} = J(C_n(q_{k+1}^n),
 // q_f^{n+1}, q_c^{*,n+1}); without qf it is the plain coarse pass of the
-// zeroth iteration, q^{n+1} = C_n(q^n).  qn row 0 is copied from q.
-__global__ void __launch_bounds__(256) chain_kernel(const ChainInst *__restrict__ ci, int inst0,
+// zeroth iteration, q^{n+1} = C_n(q^n).  qn row 0 is copied from q.  A block
+// of CHAIN_THREADS: the product E rho of a link is spread over all its waves,
+// each taking CHAIN_ROWS rows at a time with their loads in flight together,
+// every row summed in the order of the single-instance coarse step.
+constexpr int CHAIN_THREADS = 1024;
+constexpr int CHAIN_ROWS = 4;
+
+__global__ void __launch_bounds__(CHAIN_THREADS) chain_kernel(const ChainInst *__restrict__ ci, int inst0,
                                                     const CoarseUnit *__restrict__ cu, const double *__restrict__ E,
                                                     const double *__restrict__ q, const double *__restrict__ qf,
                                                     const double *__restrict__ qcs, double *__restrict__ qn,
@@ -202,9 +208,23 @@ __global__ void __launch_bounds__(256) chain_kernel(const ChainInst *__restrict_
             rho[i] = (i == 0) ? c[1] : (i == g.cells - 1) ? 1.0 - c[g.cells - 1] : c[i + 1] - c[i];
         __syncthreads();
         const double *Es = E + (int64_t)U.e_id * g.cells * g.cells;
-        for (int r = wave; r < g.cells; r += 4) {
-            const double acc = row_dot(Es + (int64_t)r * g.cells, rho, g.cells, lane);
-            if (lane == 0) rho2[r] = acc > 0.0 ? acc : 0.0;
+        const int nw = (int)(blockDim.x >> 6);
+        for (int r0 = wave; r0 < g.cells; r0 += nw * CHAIN_ROWS) {
+            const double *rows[CHAIN_ROWS];
+            double acc[CHAIN_ROWS];
+#pragma unroll
+            for (int k = 0; k < CHAIN_ROWS; ++k) {
+                const int r = r0 + k * nw;
+                rows[k] = Es + (int64_t)(r < g.cells ? r : r0) * g.cells;
+            }
+            lane_rows_dot<CHAIN_ROWS, 4>(rows, rho, g.cells, lane, acc);
+#pragma unroll
+            for (int k = 0; k < CHAIN_ROWS; ++k) {
+                double a = acc[k];
+                for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off);
+                const int r = r0 + k * nw;
+                if (lane == 0 && r < g.cells) rho2[r] = a > 0.0 ? a : 0.0;
+            }
         }
         __syncthreads();
         masses_to_knots_block(rho2, C, g, qc);
@@ -339,6 +359,9 @@ struct Batch {
     int *mk_gseg = nullptr;
     int64_t mk_chunks = 0, mk_groups = 0;
     int *flag = nullptr;
+    int *flag_host = nullptr;  // pinned copy of flag
+    bool mk_ok = true;         // the matched-knot kernels serve this batch
+    int knot_sorts = 0;        // batched iterations whose new knots needed the sort
     int cur = 0, k = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -356,6 +379,7 @@ static void batch_free(Batch *b) {
         if (gx) (void)hipGraphExecDestroy(gx);
     for (auto &e : b->ev)
         if (e) (void)hipEventDestroy(e);
+    if (b->flag_host) (void)hipHostFree(b->flag_host);
     delete b;
 }
 
@@ -499,6 +523,22 @@ static int autotune(Batch *b, hipStream_t st) {
     return PR_OK;
 }
 
+// After a batched iteration (buffer nx holds the new states): where the
+// matched-knot kernels raised the flag, the knots of the new states come from
+// a sort of them.  The host reads the flag once per iteration instead of
+// launching the sort guarded by it, whose empty launches cost more than the
+// wait.
+static int sort_new_if_flagged(Batch *b, int nx, hipStream_t st) {
+    if (!b->mk_ok) return PR_OK;
+    PR_HIP(hipMemcpyAsync(b->flag_host, b->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PR_HIP(hipStreamSynchronize(st));
+    if (*b->flag_host == 0) return PR_OK;
+    SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
+    PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, b->Q, b->qR, nullptr, b->ws, st));
+    b->knot_sorts += 1;
+    return PR_OK;
+}
+
 // One iteration: mode 0 = batched launches, 1 = instance by instance.
 static int iterate_once(Batch *b, int mode, hipStream_t st) {
     const int c = b->cur, nx = 1 - c, Q = b->Q;
@@ -518,7 +558,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
         hipLaunchKernelGGL(m2k_units, dim3(b->total_slices), dim3(256), sizeof(double) * (2 * g.cells + 1), st,
                            (const double *)b->rho_b, (const CoarseUnit *)b->cu, b->qcs, g);
         PR_LAUNCHED();
-        hipLaunchKernelGGL(chain_kernel, dim3(b->B), dim3(256), lds_chain(g), st, (const ChainInst *)b->chain, 0,
+        hipLaunchKernelGGL(chain_kernel, dim3(b->B), dim3(CHAIN_THREADS), lds_chain(g), st, (const ChainInst *)b->chain, 0,
                            (const CoarseUnit *)b->cu, (const double *)b->E, (const double *)b->q,
                            (const double *)b->qf, (const double *)b->qcs, b->qn, g);
         PR_LAUNCHED();
@@ -526,14 +566,15 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
                            (const MatchSeg *)b->mseg, (const int *)b->mtile, 0, (const double *)b->qn,
                            (const double *)b->qf, Q, (const uint32_t *)b->rank, b->x[nx]);
         PR_LAUNCHED();
-        // knots of the new states: from the fine results' sort, the sort of
-        // the new states running only where the device flags a failure
+        // knots of the new states: from the fine results' sort; where that
+        // cannot isolate every order statistic the device raises the flag and
+        // the host sorts the new states after the iteration (sort_new_if_flagged)
         const int mk = matched_knots_segments(b->ws, b->total_x, (int)b->seg_f_h.size(), b->mk_seg, b->mk_gseg,
                                               b->mk_chunks, b->mk_groups, Q, b->qn, b->qf, b->qR, b->flag, st);
         if (mk != PR_OK && mk != PR_E_UNSUPPORTED) return mk;
-        SortLayout LG = L;
-        if (mk == PR_OK) LG.guard = b->flag;
-        PR_CHECK(restrict_segments(b->x[nx], PR_F64, LG, b->total_x, b->tiles_f, Q, b->qR, nullptr, b->ws, st));
+        b->mk_ok = mk == PR_OK;
+        if (!b->mk_ok)
+            PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, Q, b->qR, nullptr, b->ws, st));
         hipLaunchKernelGGL(copy_f64, dim3(64), dim3(256), 0, st, (const double *)b->qn, b->q,
                            (int64_t)b->total_rows * (Q + 1));
         PR_LAUNCHED();
@@ -558,7 +599,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
             hipLaunchKernelGGL(m2k_units, dim3(K), dim3(256), sizeof(double) * (2 * g.cells + 1), st,
                                (const double *)b->rho_b, cu, b->qcs, g);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(chain_kernel, dim3(1), dim3(256), lds_chain(g), st, (const ChainInst *)b->chain, i,
+            hipLaunchKernelGGL(chain_kernel, dim3(1), dim3(CHAIN_THREADS), lds_chain(g), st, (const ChainInst *)b->chain, i,
                                (const CoarseUnit *)b->cu, (const double *)b->E, (const double *)b->q,
                                (const double *)b->qf, (const double *)b->qcs, b->qn, g);
             PR_LAUNCHED();
@@ -734,6 +775,7 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
         PR_CHECK(upload(b->mk_seg, mk, st));
         PR_CHECK(upload(b->mk_gseg, gseg, st));
         PB_ALLOC(b->flag, sizeof(int));
+        PR_HIP(hipHostMalloc((void **)&b->flag_host, sizeof(int), hipHostMallocDefault));
     }
     // the sort arrays are indexed like the states (segment bases are state offsets)
     int64_t max_inst_keys = 0, max_inst_tiles = 0;
@@ -776,7 +818,7 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
         PR_CHECK(init_ensemble(&sde[i], seed, b->inst_id[i], ni, b->x[0] + xo_i, b->y[0] + xo_i, st));
         PR_CHECK(restrict_quantiles(b->x[0] + xo_i, PR_F64, ni, 1, b->Q, nullptr, b->q + (int64_t)r0 * (b->Q + 1),
                                     b->rank + xo_i, nullptr, nullptr, nullptr, nullptr, b->ws, st));
-        hipLaunchKernelGGL(chain_kernel, dim3(1), dim3(256), lds_chain(b->g), st, (const ChainInst *)b->chain, i,
+        hipLaunchKernelGGL(chain_kernel, dim3(1), dim3(CHAIN_THREADS), lds_chain(b->g), st, (const ChainInst *)b->chain, i,
                            (const CoarseUnit *)b->cu, (const double *)b->E, (const double *)b->q, nullptr, nullptr,
                            b->q, b->g);
         PR_LAUNCHED();
@@ -882,6 +924,7 @@ extern "C" int pr_parareal_batch_iterate(void *hv, int n_iter, int mode, double 
     for (int it = 0; it < n_iter; ++it) {
         if (mode == PR_LAUNCH_GRAPH) PR_HIP(hipGraphLaunch(b->graph[b->cur], st));
         else PR_CHECK(iterate_once(b, mode == PR_LAUNCH_PER_INSTANCE ? 1 : 0, st));
+        if (mode != PR_LAUNCH_PER_INSTANCE) PR_CHECK(sort_new_if_flagged(b, 1 - b->cur, st));
         b->cur = 1 - b->cur;
         b->k += 1;
     }

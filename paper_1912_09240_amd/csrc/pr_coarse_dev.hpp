@@ -25,6 +25,36 @@ __device__ __forceinline__ double lane_row_dot(const double *__restrict__ row, c
     return acc;
 }
 
+// The lane's shares of R rows at once (row k at rows[k]): every row's
+// multiply-adds run in the element order of lane_row_dot, so each sum has
+// its bits; the loads of U elements of all R rows are issued before any of
+// them is used, R U loads in flight per lane.
+template <int R, int U>
+__device__ __forceinline__ void lane_rows_dot(const double *const *rows, const double *v, int n, int lane,
+                                              double *acc) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    for (int j0 = lane; j0 < n; j0 += 64 * U) {
+        double e[R][U];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * 64;
+                e[k][u] = j < n ? rows[k][j] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u * 64;
+            if (j < n) {
+                const double vj = v[j];
+#pragma unroll
+                for (int k = 0; k < R; ++k) acc[k] = fma(e[k][u], vj, acc[k]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Knots -> cell masses (H).  c(x) = 0 for x <= q_0, 1 for x > q_Q, else
 // (j + (x - q_j)/(q_{j+1} - q_j))/Q with j the largest index with q_j < x

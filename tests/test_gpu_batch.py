@@ -152,3 +152,42 @@ def test_batch_exactness(torch_dev):
             torch.cuda.synchronize()
             assert np.array_equal(st[k][0], x.cpu().numpy()), (i, t)
             k += 1
+
+
+def test_batch_equals_single_instance_handles_bitwise(torch_dev):
+    """Each instance of a batch against its own single-instance driver
+    (pr_parareal_create with the same seed and instance word): the batched
+    fine launch, segmented sorts, coarse steps, one-block chains and matching
+    carry the arithmetic of the single-instance kernels in the same order, so
+    knots and states agree bit for bit after three iterations."""
+    torch = torch_dev
+    _say("batch vs single-instance handles")
+    inst = INSTANCES[:3]
+    ids = [11, 3, 40]
+    h = _make(torch, 0, inst, ids=ids)
+    try:
+        pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_GRAPH)
+        st = _states(torch, h, inst)
+    finally:
+        pr.pr_parareal_batch_destroy(h)
+    k = 0
+    for (eps, lam, n, K, T), iid in zip(inst, ids):
+        dt = eps / 20
+        S = int(round(T / dt))
+        hs = pr.pr_parareal_create(pr.Sde(lam=lam, eps=eps, beta=2.0), pr.Schedule(S, K, T / S),
+                                   pr.Grid(n_cells=CELLS, n_q=NQ), 7, iid, n)
+        try:
+            pr.pr_parareal_iterate(hs, 3)
+            for t in range(K + 1):
+                x = torch.empty(n, dtype=torch.float64, device="cuda")
+                y = torch.empty(n, dtype=torch.float64, device="cuda")
+                q = torch.empty(NQ + 1, dtype=torch.float64, device="cuda")
+                pr.pr_parareal_state(hs, t, x=x, y=y, q=q)
+                torch.cuda.synchronize()
+                a, b, c = st[k]
+                k += 1
+                assert np.array_equal(c, q.cpu().numpy()), (iid, t)
+                assert np.array_equal(a, x.cpu().numpy()), (iid, t)
+                assert np.array_equal(b, y.cpu().numpy()), (iid, t)
+        finally:
+            pr.pr_parareal_destroy(hs)
