@@ -181,13 +181,39 @@ def adjoint_measure(torch, pr):
     t_adj = ev[2].elapsed_time(ev[3]) / 1e3
     t_plain = ev[4].elapsed_time(ev[5]) / 1e3
     total = t_fwd + t_obs + t_adj
+    jac256 = jac.clone()
+    # memory for time: checkpoints every 8 steps are the reverse sweep's tape
+    # starts, which drops its first recomputation (1250 x 2 x 2^20 doubles)
+    del ck, wsa
+    torch.cuda.empty_cache()
+    e8 = 8
+    ck8 = torch.empty(((S + e8 - 1) // e8, 2, n), dtype=torch.float64, device="cuda")
+    ws8 = torch.empty(pr.pr_adjoint_workspace_size(n, e8, k), dtype=torch.uint8, device="cuda")
+    for rep in range(2):
+        pr.pr_init_ensemble(sde, a["seed"], 0, n, x, y)
+        ev[0].record()
+        pr.pr_fine_checkpoint(sde, sched, a["seed"], 0, n, x, y, ck8, e8)
+        ev[1].record()
+        pr.pr_observables(x, n, list(a["alpha"]), obs, wso, seed_x=seeds)
+        ev[2].record()
+        pr.pr_fine_adjoint(sde, sched, a["seed"], 0, n, ck8, e8, seeds, k, jac, ws8)
+        ev[3].record()
+        torch.cuda.synchronize()
+    t_fwd8 = ev[0].elapsed_time(ev[1]) / 1e3
+    t_adj8 = ev[2].elapsed_time(ev[3]) / 1e3
+    jac_rel = float(((jac - jac256).abs().max(dim=1).values / jac256.abs().max(dim=1).values).max())
+    every8 = dict(checkpoint_bytes=ck8.numel() * 8, forward_ckpt_s=t_fwd8, reverse_s=t_adj8,
+                  reverse_over_forward=t_adj8 / t_fwd8, jacobian_rel_diff_vs_every256=jac_rel)
+    del ck8, ws8
+    torch.cuda.empty_cache()
     return dict(workload="adjoint of the 2-D SDE (lambda=1, beta=2, eps=0.1), P=2^20 FP64, 1e4 steps of dt=1e-4, "
                          "checkpoints every 256 steps, observables mean X_T^2 and quantiles 0.1/0.5/0.9, "
                          "4x4 Jacobian w.r.t. (lambda, eps, beta, c3) in one reverse sweep",
                 fwd_plus_adjoint_particle_steps_per_s=n * S / total, forward_ckpt_s=t_fwd, observables_s=t_obs,
                 reverse_s=t_adj, plain_forward_s=t_plain, reverse_over_forward=t_adj / t_fwd,
                 ratio_to_8_crn_fd_forwards=total / (8 * t_plain),
-                jacobian=jac.cpu().tolist(), observables=obs.cpu().tolist())
+                ckpt_every_8=every8,
+                jacobian=jac256.cpu().tolist(), observables=obs.cpu().tolist())
 
 
 BATCH = dict(count=256, T=2.0, beta=2.0, cells=200, nq=100, seed=0)
@@ -645,7 +671,12 @@ def summary_line(d, args, config):
                                     one_thread_value=_sig(cb.get("one_thread", {}).get("value")))
     a = d["adjoint"]
     line["adjoint"] = {k: (_sig(v) if isinstance(v, float) else v) for k, v in a.items()
-                       if k not in ("workload", "jacobian", "observables")}
+                       if k not in ("workload", "jacobian", "observables", "ckpt_every_8")}
+    if "ckpt_every_8" in a:
+        e8 = a["ckpt_every_8"]
+        line["adjoint"]["ckpt_every_8"] = dict(reverse_over_forward=_sig(e8["reverse_over_forward"]),
+                                               reverse_s=_sig(e8["reverse_s"]),
+                                               checkpoint_bytes=e8["checkpoint_bytes"])
     b = d["batched"]
     line["batched"] = dict(sweep_ms_graph=_sig(b["sweep_ms_graph"]), sweep_ms_batched=_sig(b["sweep_ms_batched"]),
                            sweep_ms_per_instance=_sig(b["sweep_ms_per_instance"]),

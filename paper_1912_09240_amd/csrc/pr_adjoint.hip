@@ -5,7 +5,9 @@
 // with the noise z held fixed (common random numbers), including the
 // dependence of the initial law Y0 = X0 + beta^-1/2 z on beta.
 //
-// Memory plan: the forward pass stores the state every E steps (E = 256).
+// Memory plan: the forward pass stores the state every E steps (E = 256 for
+// the differentiated workload; with E <= 8 the checkpoints are the tapes'
+// starts and the first recomputation below drops out).
 // The reverse kernel walks every particle through the segments backwards.
 // For one segment it recomputes the E steps once, writing the state every
 // AD_SUB = 8 steps to a small global scratch; then for each 8-step
@@ -39,23 +41,48 @@ __device__ __forceinline__ void em_step_d1(double &x, double &y, const EmCoef<do
 }
 
 // Forward over all steps [0, S) of one segment in time, with checkpoints.
+// Two particles per thread (p and p + blockDim), as in the fine propagator,
+// so that the two steps' instruction streams interleave.
+constexpr int CK_PPT = 2;
+
 __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, double *__restrict__ y, int64_t n,
                                                        int64_t S, int every, double *__restrict__ ckpt,
                                                        EmCoef<double> ec, Key key, uint32_t inst) {
     __shared__ NoiseTab tab;
     load_noise_tab(tab);
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    double xv = x[p], yv = y[p];
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * CK_PPT + threadIdx.x;
+    double xv[CK_PPT], yv[CK_PPT];
+    bool live[CK_PPT];
+    int64_t pp[CK_PPT];
+#pragma unroll
+    for (int q = 0; q < CK_PPT; ++q) {
+        pp[q] = base + (int64_t)q * blockDim.x;
+        live[q] = pp[q] < n;
+        const int64_t pc = live[q] ? pp[q] : 0;
+        xv[q] = x[pc];
+        yv[q] = y[pc];
+    }
     int64_t cidx = 0;
     for (int64_t m0 = 0; m0 < S; m0 += every, ++cidx) {
-        ckpt[(cidx * 2) * n + p] = xv;
-        ckpt[(cidx * 2 + 1) * n + p] = yv;
+#pragma unroll
+        for (int q = 0; q < CK_PPT; ++q)
+            if (live[q]) {
+                ckpt[(cidx * 2) * n + pp[q]] = xv[q];
+                ckpt[(cidx * 2 + 1) * n + pp[q]] = yv[q];
+            }
         const int64_t m1 = m0 + every < S ? m0 + every : S;
-        for (int64_t m = m0; m < m1; ++m) em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
+        for (int64_t m = m0; m < m1; ++m) {
+#pragma unroll
+            for (int q = 0; q < CK_PPT; ++q)
+                em_step_d1(xv[q], yv[q], ec, tab, key, inst, (uint32_t)m, (uint32_t)pp[q]);
+        }
     }
-    x[p] = xv;
-    y[p] = yv;
+#pragma unroll
+    for (int q = 0; q < CK_PPT; ++q)
+        if (live[q]) {
+            x[pp[q]] = xv[q];
+            y[pp[q]] = yv[q];
+        }
 }
 
 template <int NS>
@@ -82,22 +109,30 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
         for (int seg = n_ckpt - 1; seg >= 0; --seg) {
             const int64_t m0 = (int64_t)seg * every;
             const int64_t m1 = m0 + every < S ? m0 + every : S;
-            // level 1: states every AD_SUB steps of this segment into the scratch
-            double xv = ckpt[(2 * (int64_t)seg) * n + p], yv = ckpt[(2 * (int64_t)seg + 1) * n + p];
-            int nsub = 0;
-            for (int64_t ms = m0; ms < m1; ms += AD_SUB, ++nsub) {
-                sub[(2 * (int64_t)nsub) * n + p] = xv;
-                sub[(2 * (int64_t)nsub + 1) * n + p] = yv;
-                const int64_t me = ms + AD_SUB < m1 ? ms + AD_SUB : m1;
-                for (int64_t m = ms; m < me; ++m) em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
+            // level 1: states every AD_SUB steps of this segment into the
+            // scratch; a segment of at most AD_SUB steps is one tape, which
+            // starts from the checkpoint itself (checkpoints that close
+            // trade memory for this whole recomputation)
+            int nsub = 1;
+            if (every > AD_SUB) {
+                double xv = ckpt[(2 * (int64_t)seg) * n + p], yv = ckpt[(2 * (int64_t)seg + 1) * n + p];
+                nsub = 0;
+                for (int64_t ms = m0; ms < m1; ms += AD_SUB, ++nsub) {
+                    sub[(2 * (int64_t)nsub) * n + p] = xv;
+                    sub[(2 * (int64_t)nsub + 1) * n + p] = yv;
+                    const int64_t me = ms + AD_SUB < m1 ? ms + AD_SUB : m1;
+                    for (int64_t m = ms; m < me; ++m)
+                        em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
+                }
             }
             // level 2: each sub-segment, last first
             for (int j = nsub - 1; j >= 0; --j) {
                 const int64_t ms = m0 + (int64_t)j * AD_SUB;
                 const int L = (int)((m1 - ms) < AD_SUB ? (m1 - ms) : AD_SUB);
                 double tx[AD_SUB + 1], ty[AD_SUB + 1];
-                tx[0] = sub[(2 * (int64_t)j) * n + p];
-                ty[0] = sub[(2 * (int64_t)j + 1) * n + p];
+                const double *t0 = every > AD_SUB ? sub + (2 * (int64_t)j) * n : ckpt + (2 * (int64_t)seg) * n;
+                tx[0] = t0[p];
+                ty[0] = t0[n + p];
 #pragma unroll
                 for (int i = 0; i < AD_SUB; ++i) {
                     double a = tx[i], b = ty[i];
@@ -294,7 +329,8 @@ extern "C" int pr_fine_checkpoint(const pr_sde *sde, const pr_schedule *sched, u
     PR_REQUIRE(n >= 1 && n <= 0xFFFFFFFFll, "n must be in [1, 2^32)");
     PR_REQUIRE(ckpt_every >= 1 && ckpt_every <= 1 << 20, "ckpt_every must be in [1, 2^20]");
     PR_REQUIRE(x && y && ckpt, "x, y and ckpt must be non-NULL");
-    hipLaunchKernelGGL(fwd_ckpt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream),
+    hipLaunchKernelGGL(fwd_ckpt_kernel, dim3((unsigned)((n + 256 * CK_PPT - 1) / (256 * CK_PPT))), dim3(256), 0,
+                       as_stream(stream),
                        (double *)x, (double *)y, n, sched->total_steps, ckpt_every, ckpt,
                        make_coef<double>(sde, sched->dt), make_key(seed), instance);
     PR_LAUNCHED();

@@ -24,6 +24,7 @@
 // (the ranks through a staging buffer instead of stores to random addresses,
 // rs_rank_bucket and rs_rank_place); the complete sort follows, guarded by a
 // flag that the fix-up raises only for a run longer than it handles.
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -414,6 +415,451 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
                     if (perm_out) perm_out[T.base + gpos[r]] = v;
                 }
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Splitter sort of large FP64 ensembles (equal lengths, n >= SS_MIN_N): the
+// keys are first distributed over SS_B buckets by splitters drawn from a
+// sample, then every bucket is ordered on its own in LDS.
+//   ss_sample_runs  SS_RUNS blocks per ensemble, each sorting SS_RUN keys of
+//                   the sample (positions i n / (SS_RUNS SS_RUN)) in LDS and
+//                   keeping its SS_B quantile keys;
+//   ss_splitters    splitter b = the mean over the runs of their b-th
+//                   quantile value (non-decreasing in b, as every run's
+//                   quantiles are);
+//   ss_count        bucket histogram of every tile (the moments and the cell
+//                   histogram fused into this first read of the values);
+//   rs_rowscan      tile offsets and bucket totals, as for a radix pass;
+//   ss_scatter      stable scatter of (key, particle) into the buckets, so
+//                   that inside a bucket the particles keep their order;
+//   ss_bucket_sort  one block per bucket: the keys go to value sub-buckets
+//                   (linear in the value between the bucket's bounds, which
+//                   keeps the order), every key counts the keys of its
+//                   sub-bucket that precede it by (key, position in the
+//                   bucket), and the bucket is written out in order with its
+//                   permutation.
+// A bucket above SS_CAP keys or a sub-bucket above SS_SUBMAX raises the flag
+// that runs the complete radix sort behind it.  Compared with four radix
+// passes and the fix-up this moves about half the bytes per key.
+// ---------------------------------------------------------------------------
+constexpr int SS_B = 256;
+constexpr int SS_RUNS = 16;
+constexpr int SS_RUN = 1024;
+constexpr int SS_BT = 512;                  // threads of a bucket block
+constexpr int SS_IT = 15;                   // keys per thread of a bucket block
+constexpr int SS_CAP = SS_BT * SS_IT;       // 7680: two bucket blocks share a CU's LDS
+constexpr int SS_SUB = 1024;
+constexpr int SS_SUBMAX = 512;
+constexpr int64_t SS_MIN_N = (int64_t)1 << 16;
+static_assert(SS_B == RS_RADIX, "buckets take the place of a radix pass's digits");
+static_assert(SS_SUB == 2 * SS_BT, "two sub-bucket counts per thread");
+
+// Bucket of a key: the number of splitters sp[1..SS_B-1] at or below it.
+__device__ __forceinline__ uint32_t ss_bucket_of(uint64_t key, const uint64_t *sp) {
+    uint32_t b = 0;
+#pragma unroll
+    for (uint32_t step = SS_B / 2; step >= 1; step >>= 1)
+        if (sp[b + step] <= key) b += step;
+    return b;
+}
+
+__global__ void __launch_bounds__(SS_RUN / 2) ss_sample_runs(const double *__restrict__ x, SortLayout L,
+                                                            uint64_t *__restrict__ runq) {
+    __shared__ uint64_t sk[SS_RUN];
+    const int r = blockIdx.x, s = blockIdx.y, t = threadIdx.x;
+    const int64_t n = L.n, total = (int64_t)SS_RUNS * SS_RUN;
+    const double *xs = x + (int64_t)s * n;
+    for (int i = t; i < SS_RUN; i += blockDim.x) {
+        const int64_t g = (int64_t)r * SS_RUN + i;
+        sk[i] = key_of(xs[g * n / total]);
+    }
+    __syncthreads();
+    for (int size = 2; size <= SS_RUN; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;  // one pair per thread
+            const bool up = (lo & size) == 0;
+            const uint64_t a = sk[lo], b = sk[hi];
+            if ((a > b) == up) {
+                sk[lo] = b;
+                sk[hi] = a;
+            }
+            __syncthreads();
+        }
+    for (int b = t; b < SS_B; b += blockDim.x)
+        runq[((int64_t)s * SS_RUNS + r) * SS_B + b] = sk[b * (SS_RUN / SS_B)];
+}
+
+// Splitter b: the mean over the runs of their b-th quantile value, each
+// value first clamped to the finite range (infinities and NaN to the end of
+// the range their key sorts to).  The clamped value is non-decreasing in the
+// key, so the means are non-decreasing in b; averaging in the value domain
+// keeps the splitters where the values lie (the key domain is far from
+// linear in the value around 0).
+__global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict__ runq, uint64_t *__restrict__ split) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x, b = threadIdx.x;
+    double acc = 0.0;
+    for (int r = 0; r < SS_RUNS; ++r) {
+        const uint64_t k = runq[((int64_t)s * SS_RUNS + r) * SS_B + b];
+        double v = value_of(k);
+        if (v != v) v = (k >> 63) ? 1.79e308 : -1.79e308;
+        v = fmin(fmax(v, -1.79e308), 1.79e308);
+        acc += v / (double)SS_RUNS;
+    }
+    split[(int64_t)s * SS_B + b] = b == 0 ? 0ull : key_of(acc);
+}
+
+__global__ void __launch_bounds__(RS_THREADS)
+ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, SortLayout L,
+         uint32_t *__restrict__ counts, double *__restrict__ mom_part, HistArgs ha) {
+    constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
+    __shared__ uint32_t h[RS_WAVES][2][RS_RADIX];
+    __shared__ double wsum[RS_WAVES][4];
+    __shared__ uint64_t sp[SS_B];
+    extern __shared__ uint32_t cell_h[];
+    const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < RS_WAVES * 2 * RS_RADIX; i += RS_THREADS) (&h[0][0][0])[i] = 0;
+    for (int i = tid; i < SS_B; i += RS_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
+    const bool do_hist = ha.hist != nullptr;
+    if (do_hist)
+        for (int i = tid; i < ha.cells; i += RS_THREADS) cell_h[i] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
+    double in[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        in[i] = idx < T.n ? src[T.base + idx] : 0.0;
+    }
+    // every key's bucket first (loads of LDS only, so the searches of the
+    // tile's keys overlap), then the counting
+    uint32_t bk[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) bk[i] = ss_bucket_of(key_of(in[i]), sp);
+    double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        if (idx < T.n) {
+            const double xv = in[i];
+            const double x2 = xv * xv;
+            s1 += xv;
+            s2 += x2;
+            s3 += x2 * xv;
+            s4 += x2 * x2;
+            if (do_hist) {
+                double c = floor((xv - ha.lo) * ha.inv_h);
+                c = fmin(fmax(c, 0.0), (double)(ha.cells - 1));
+                atomicAdd(&cell_h[(int)c], 1u);
+            }
+            atomicAdd(&h[wave][lane & 1][bk[i]], 1u);
+        }
+    }
+    if (mom_part != nullptr) {
+        for (int off = 32; off >= 1; off >>= 1) {  // fixed butterfly, as in rs_count
+            s1 += __shfl_xor(s1, off);
+            s2 += __shfl_xor(s2, off);
+            s3 += __shfl_xor(s3, off);
+            s4 += __shfl_xor(s4, off);
+        }
+        if (lane == 0) {
+            wsum[wave][0] = s1;
+            wsum[wave][1] = s2;
+            wsum[wave][2] = s3;
+            wsum[wave][3] = s4;
+        }
+    }
+    __syncthreads();
+    {
+        const int d = tid;
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) c += h[w][0][d] + h[w][1][d];
+        counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] = c;
+    }
+    if (mom_part != nullptr && tid < 4) {
+        double t = 0;
+        for (int w = 0; w < RS_WAVES; ++w) t += wsum[w][tid];
+        mom_part[(T.tile0 + T.blk) * 4 + tid] = t;
+    }
+    if (do_hist)
+        for (int i = tid; i < ha.cells; i += RS_THREADS)
+            if (cell_h[i]) atomicAdd(&ha.hist[(int64_t)T.seg * ha.cells + i], cell_h[i]);
+}
+
+// Stable scatter of (key, particle) into the buckets: the arithmetic of
+// rs_scatter's first pass with the bucket in place of the digit.
+__global__ void __launch_bounds__(RS_THREADS)
+ss_scatter(const double *__restrict__ src, const uint64_t *__restrict__ split, uint64_t *__restrict__ keys_out,
+           uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
+           const uint32_t *__restrict__ totals, SortLayout L, uint32_t *__restrict__ bstart) {
+    constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
+    __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t wbase[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t gdelta[RS_RADIX];
+    __shared__ uint32_t wtot[RS_WAVES];
+    __shared__ uint64_t stage[TILE];
+    __shared__ uint8_t sdig[TILE];
+    __shared__ uint64_t sp[SS_B];
+
+    const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int i = tid; i < SS_B; i += RS_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
+    for (int i = lane; i < RS_RADIX; i += 64) wcnt[wave][i] = 0;
+    __syncthreads();
+
+    uint64_t key[ITEMS];
+    uint32_t dig[ITEMS], rnk[ITEMS];
+    double in[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        in[i] = idx < T.n ? src[T.base + idx] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = t0 + i * 64 + lane < T.n;
+        key[i] = valid ? key_of(in[i]) : 0ull;
+        dig[i] = valid ? ss_bucket_of(key[i], sp) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const bool valid = t0 + i * 64 + lane < T.n;
+        const uint32_t d = dig[i];
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t base = 0;
+        if (valid) base = wcnt[wave][d];
+        rnk[i] = base + (uint32_t)__popcll(peers & lt);
+        wave_sync();
+        if (valid && lane == 63 - __clzll(peers)) wcnt[wave][d] = base + (uint32_t)__popcll(peers);
+        wave_sync();
+    }
+    __syncthreads();
+    {
+        const int d = tid;
+        uint32_t c[RS_WAVES], tot = 0;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            c[w] = wcnt[w][d];
+            tot += c[w];
+        }
+        const uint32_t lstart = block_exclusive_256(tot, wtot);
+        const uint32_t dbase = block_exclusive_256(totals[(int64_t)T.seg * RS_RADIX + d], wtot);
+        uint32_t acc = lstart;
+#pragma unroll
+        for (int w = 0; w < RS_WAVES; ++w) {
+            wbase[w][d] = acc;
+            acc += c[w];
+        }
+        gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - lstart;
+        if (T.blk == 0) bstart[(int64_t)T.seg * RS_RADIX + d] = dbase;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (t0 + i * 64 + lane < T.n) {
+            const uint32_t j = wbase[wave][dig[i]] + rnk[i];
+            stage[j] = key[i];
+            sdig[j] = (uint8_t)dig[i];
+        }
+    __syncthreads();
+    const int64_t rem = T.n - (int64_t)T.blk * TILE;
+    const int tile_n = rem < TILE ? (int)rem : TILE;
+    uint32_t gpos[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int j = tid + r * RS_THREADS;
+        gpos[r] = 0xFFFFFFFFu;
+        if (j < tile_n) {
+            const uint32_t g = (uint32_t)j + gdelta[sdig[j]];
+            if ((int64_t)g < T.n) {  // always true for a consistent scan
+                gpos[r] = g;
+                keys_out[T.base + g] = stage[j];
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *sv = (uint32_t *)stage;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (t0 + i * 64 + lane < T.n) sv[wbase[wave][dig[i]] + rnk[i]] = (uint32_t)(t0 + i * 64 + lane);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int j = tid + r * RS_THREADS;
+        if (j < tile_n && gpos[r] != 0xFFFFFFFFu) vals_out[T.base + gpos[r]] = sv[j];
+    }
+}
+
+// Reduction of one value per thread over a block of SS_BT.
+template <typename V, typename Op>
+__device__ __forceinline__ V ss_block_reduce(V v, V *red, Op op) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1) v = op(v, (V)__shfl_xor(v, off));
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    V r = red[0];
+    for (int w = 1; w < SS_BT / 64; ++w) r = op(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SS_BT)
+ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ bvals,
+               const uint32_t *__restrict__ totals, const uint32_t *__restrict__ bstart,
+               const uint64_t *__restrict__ split, SortLayout L, uint64_t *__restrict__ keys_out,
+               uint32_t *__restrict__ perm_out, uint32_t *__restrict__ rank_out, double *__restrict__ xs_out,
+               int *__restrict__ flag) {
+    __shared__ uint64_t sk[SS_CAP];
+    __shared__ uint16_t spos[SS_CAP];          // position of the key in the bucket's input
+    __shared__ uint16_t sstart[SS_SUB];
+    __shared__ uint32_t cursor[SS_SUB / 2];   // two 16-bit counters per word (sub-buckets 2i, 2i+1)
+    __shared__ uint64_t red64[SS_BT / 64];
+    __shared__ uint32_t red32[SS_BT / 64];
+    __shared__ int too_big;
+    const int s = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const uint32_t size = totals[(int64_t)s * SS_B + b];
+    if (size == 0) return;
+    if (size > (uint32_t)SS_CAP) {
+        if (tid == 0) *flag = 1;
+        return;
+    }
+    const uint32_t start = bstart[(int64_t)s * SS_B + b];
+    const int64_t base = (int64_t)s * L.n + start;
+    for (int i = tid; i < SS_SUB / 2; i += SS_BT) cursor[i] = 0;
+    if (tid == 0) too_big = 0;
+    uint64_t k[SS_IT];
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        k[i] = idx < size ? bkeys[base + idx] : ~0ull;
+    }
+    // bounds of the bucket's values: its splitters inside, its extremes at
+    // the two ends of the ensemble
+    uint64_t kmin, kmax;
+    if (b > 0 && b < SS_B - 1) {
+        kmin = split[(int64_t)s * SS_B + b];
+        kmax = split[(int64_t)s * SS_B + b + 1];
+    } else {
+        kmin = ~0ull;
+        kmax = 0ull;
+#pragma unroll
+        for (int i = 0; i < SS_IT; ++i)
+            if ((uint32_t)tid + (uint32_t)i * SS_BT < size) {
+                kmin = k[i] < kmin ? k[i] : kmin;
+                kmax = k[i] > kmax ? k[i] : kmax;
+            }
+        kmin = ss_block_reduce<uint64_t>(kmin, red64, [](uint64_t a, uint64_t c) { return a < c ? a : c; });
+        kmax = ss_block_reduce<uint64_t>(kmax, red64, [](uint64_t a, uint64_t c) { return a > c ? a : c; });
+    }
+    // value sub-buckets: floor((x - lo) SS_SUB / (hi - lo)) is non-decreasing
+    // in x (every rounded operation is), so they keep the order; equal values
+    // share one.  Bounds that are not finite put every key in one.
+    const double lo = value_of(kmin), hi = value_of(kmax);
+    const double span = hi - lo;
+    const double scale = (span > 0.0 && span <= 1.79e308) ? (double)SS_SUB / span : 0.0;
+    __syncthreads();
+    uint16_t sub[SS_IT];
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        sub[i] = 0;
+        if ((uint32_t)tid + (uint32_t)i * SS_BT < size) {
+            const double t = (value_of(k[i]) - lo) * scale;
+            sub[i] = (uint16_t)(t >= (double)SS_SUB ? SS_SUB - 1 : (t > 0.0 ? (int)t : 0));
+            atomicAdd(&cursor[sub[i] >> 1], 1u << (16 * (sub[i] & 1)));
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the sub-bucket counts (two per thread), their maximum
+    {
+        const uint32_t c0 = cursor[tid] & 0xFFFFu, c1 = cursor[tid] >> 16;
+        if (c0 > (uint32_t)SS_SUBMAX || c1 > (uint32_t)SS_SUBMAX) too_big = 1;
+        const uint32_t c = c0 + c1;
+        const int lane = tid & 63, wave = tid >> 6;
+        uint32_t inc = c;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(inc, off);
+            if (lane >= off) inc += t;
+        }
+        if (lane == 63) red32[wave] = inc;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (int w = 0; w < wave; ++w) pre += red32[w];
+        const uint32_t e0 = pre + inc - c;
+        sstart[2 * tid] = (uint16_t)e0;
+        sstart[2 * tid + 1] = (uint16_t)(e0 + c0);
+        cursor[tid] = e0 | ((e0 + c0) << 16);
+        __syncthreads();
+    }
+    if (too_big) {
+        if (tid == 0) *flag = 1;
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        if (idx < size) {
+            const uint32_t sh = 16 * (sub[i] & 1);
+            const uint32_t slot = (atomicAdd(&cursor[sub[i] >> 1], 1u << sh) >> sh) & 0xFFFFu;
+            sk[slot] = k[i];
+            spos[slot] = (uint16_t)idx;
+        }
+    }
+    __syncthreads();
+    // place: the keys of the sub-bucket before this one by (key, position in
+    // the bucket's input, which is the particles' order)
+    uint16_t fin[SS_IT];
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        fin[i] = 0xFFFF;
+        if (idx < size) {
+            const uint32_t a = sstart[sub[i]], e = (cursor[sub[i] >> 1] >> (16 * (sub[i] & 1))) & 0xFFFFu;
+            uint32_t r = a;
+            for (uint32_t j = a; j < e; ++j) {
+                const uint64_t kj = sk[j];
+                r += (kj < k[i] || (kj == k[i] && spos[j] < idx)) ? 1u : 0u;
+            }
+            fin[i] = (uint16_t)r;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i)
+        if (fin[i] != 0xFFFF) {
+            sk[fin[i]] = k[i];
+            spos[fin[i]] = (uint16_t)((uint32_t)tid + (uint32_t)i * SS_BT);
+        }
+    __syncthreads();
+    // the particles of all output slots are gathered first (one load per
+    // slot, all in flight together), then every output is stored
+    uint64_t ok[SS_IT];
+    uint32_t op[SS_IT];
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        ok[i] = idx < size ? sk[idx] : 0ull;
+        op[i] = idx < size ? bvals[base + spos[idx]] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        if (idx < size) {
+            keys_out[base + idx] = ok[i];
+            if (xs_out) xs_out[base + idx] = value_of(ok[i]);
+            if (perm_out) perm_out[base + idx] = op[i];
+            if (rank_out) rank_out[(int64_t)s * L.n + op[i]] = start + idx;
         }
     }
 }
@@ -1007,7 +1453,8 @@ int64_t sort_tiles(int64_t n) {
 size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload) {
     const size_t ks = precision == PR_F32 ? 4 : 8;
     size_t b = align256(total_keys * ks) * 2 + align256((size_t)total_tiles * RS_RADIX * 4) +
-               align256((size_t)nseg * RS_RADIX * 4) + align256((size_t)total_tiles * 4 * 8) + 256 + 256;
+               align256((size_t)nseg * RS_RADIX * 4) + align256((size_t)total_tiles * 4 * 8) + 256 + 256 +
+               align256((size_t)nseg * SS_B * (8 + 4 + 8 * SS_RUNS));
     if (payload) b += align256(total_keys * 4) * 2;
     return b;
 }
@@ -1048,6 +1495,9 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
     }
     int *flag = (int *)p;  // 256 bytes after the payload (or the moment) buffers
     if (payload) flag = (int *)((char *)vals[1] + align256(total_keys * 4));
+    uint64_t *split = (uint64_t *)((char *)flag + 256);  // splitters, [nseg][SS_B]
+    uint32_t *bstart = (uint32_t *)(split + (size_t)L.nseg * SS_B);  // bucket starts, [nseg][SS_B]
+    uint64_t *runq = (uint64_t *)(bstart + (size_t)L.nseg * SS_B);  // run quantiles, [nseg][SS_RUNS][SS_B]
     const dim3 grid((unsigned)total_tiles);
     const dim3 rows((unsigned)(((int64_t)L.nseg * RS_RADIX + 3) / 4));
     // outputs of the last pass (the ranks move to the staging kernels below
@@ -1104,7 +1554,40 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
         return PR_OK;
     };
     constexpr int P = KeyTraits<K>::passes;
-    if constexpr (std::is_same<K, uint64_t>::value) {
+    bool splitter = false;
+    if constexpr (std::is_same<K, uint64_t>::value && !VAR)
+        splitter = payload && L.guard == nullptr && L.n >= SS_MIN_N;
+    if (splitter) {
+        if constexpr (std::is_same<K, uint64_t>::value && !VAR) {
+            // the splitter sort, then the complete radix sort guarded by its flag
+            hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL(ss_sample_runs, dim3(SS_RUNS, (unsigned)L.nseg), dim3(SS_RUN / 2), 0, st,
+                               (const double *)x, L, runq);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL(ss_splitters, dim3((unsigned)L.nseg), dim3(SS_B), 0, st, (const uint64_t *)runq, split);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL(ss_count, grid, dim3(RS_THREADS), cell_lds, st, (const double *)x,
+                               (const uint64_t *)split, L, counts, mom ? mom_part : nullptr, ha);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL((rs_rowscan<false>), rows, dim3(256), 0, st, counts, totals, L);
+            PR_LAUNCHED();
+            hipLaunchKernelGGL(ss_scatter, grid, dim3(RS_THREADS), 0, st, (const double *)x, (const uint64_t *)split,
+                               (uint64_t *)keys[1], vals[1], (const uint32_t *)counts, (const uint32_t *)totals, L,
+                               bstart);
+            PR_LAUNCHED();
+            uint32_t *perm_fix = perm ? perm : (staged_ranks ? vals[0] : nullptr);
+            hipLaunchKernelGGL(ss_bucket_sort, dim3((unsigned)SS_B, (unsigned)L.nseg), dim3(SS_BT), 0, st,
+                               (const uint64_t *)keys[1], (const uint32_t *)vals[1], (const uint32_t *)totals,
+                               (const uint32_t *)bstart, (const uint64_t *)split, L, (uint64_t *)keys[0], perm_fix,
+                               staged_ranks ? nullptr : rank, xs, flag);
+            PR_LAUNCHED();
+            if (staged_ranks) PR_CHECK(stage_ranks(perm_fix, vals[1]));
+            SortLayout LG = L;
+            LG.guard = flag;
+            for (int j = 0; j < P; ++j) PR_CHECK(pass(LG, 8 * j, j == 0, j == P - 1, j & 1, (j + 1) & 1, false));
+        }
+    } else if constexpr (std::is_same<K, uint64_t>::value) {
         // the high 32 bits (passes 4..7, ending in buffer 1), the fix-up of
         // runs of equal high halves into buffer 0, and the complete sort
         // (also ending in buffer 0) only where a run is too long for it

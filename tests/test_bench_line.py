@@ -34,7 +34,10 @@ def _detail():
     d["adjoint"] = dict(workload="w" * 300, fwd_plus_adjoint_particle_steps_per_s=1.0123456e11,
                         forward_ckpt_s=0.0251234567, observables_s=0.00123456, reverse_s=0.0791234567,
                         plain_forward_s=0.024123456, reverse_over_forward=3.1234567,
-                        ratio_to_8_crn_fd_forwards=0.51234567, jacobian=[[1.0] * 4] * 4, observables=[1.0] * 4)
+                        ratio_to_8_crn_fd_forwards=0.51234567, jacobian=[[1.0] * 4] * 4, observables=[1.0] * 4,
+                        ckpt_every_8=dict(checkpoint_bytes=20971520000, forward_ckpt_s=0.0281234567,
+                                          reverse_s=0.0491234567, reverse_over_forward=1.7512345,
+                                          jacobian_rel_diff_vs_every256=1.234567e-15))
     d["batched"] = dict(workload="w" * 200, fine_particle_steps_per_iteration=185000000000, work_units=123456,
                         tuned_block=256, tuned_particles_per_thread=2, sweep_ms_graph=466.123456,
                         sweep_ms_batched=455.123456, sweep_ms_per_instance=1031.123456,

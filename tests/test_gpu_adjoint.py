@@ -46,7 +46,8 @@ def _forward(torch, theta, n, S, dt, every, seed=0):
     return sde, sched, x, y, ck, obs, seeds
 
 
-@pytest.mark.parametrize("n,S,every", [(4097, 1003, 256), (1000, 300, 64), (65, 17, 256)])
+@pytest.mark.parametrize("n,S,every", [(4097, 1003, 256), (1000, 300, 64), (65, 17, 256), (1000, 300, 8),
+                                       (513, 101, 5)])
 def test_adjoint_matches_oracle_tangents(torch_dev, n, S, every):
     torch = torch_dev
     _say(f"adjoint vs tangents n={n} S={S} every={every}")

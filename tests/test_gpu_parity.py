@@ -309,6 +309,42 @@ def test_restrict_large_segments(torch_dev):
         assert np.array_equal(out["q"][s], OR.hazen_knots(srt, 100))
 
 
+def _splitter_case(case, k, n):
+    rng = np.random.default_rng(700 + case)
+    x = rng.normal(0.0, 1.0, (k, n))
+    if case == 1:    # every key equal: one bucket holds the whole ensemble
+        x[:] = 0.625
+    elif case == 2:  # one far outlier stretches the last bucket's value range
+        x[:, 17] = 1e300
+    elif case == 3:  # runs of 300 equal values inside buckets
+        x = np.round(rng.normal(0.0, 1.0, (k, n)) * 60.0) / 60.0
+    elif case == 4:  # infinities and signed zeros among smooth values
+        x[:, ::997] = np.inf
+        x[:, 5::991] = -np.inf
+        x[:, 7::89] = -0.0
+        x[:, 11::97] = 0.0
+    return np.ascontiguousarray(x)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_restrict_splitter_cases(torch_dev, case):
+    """Ensembles of 2^17 particles (sorted by splitters and buckets where
+    every bucket fits, by the complete radix sort otherwise): smooth values,
+    all equal, a far outlier, long runs of ties, infinities and signed zeros.
+    Every output bit for bit against the oracle's stable sort."""
+    torch = torch_dev
+    k, n = 2, 2 ** 17
+    _say(f"restrict splitter case {case}")
+    xs = _splitter_case(case, k, n)
+    out = _restrict_gpu(torch, xs, 100)
+    for s in range(k):
+        perm, rank, srt = OR.sort_ranks(xs[s])
+        assert np.array_equal(out["perm"][s], perm), s
+        assert np.array_equal(out["rank"][s], rank), s
+        assert np.array_equal(out["xs"][s].view(np.uint64), srt.view(np.uint64)), s
+        assert np.array_equal(out["q"][s], OR.hazen_knots(srt, 100)), s
+
+
 def test_restrict_fp32(torch_dev):
     torch = torch_dev
     _say("restrict fp32")
