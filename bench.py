@@ -139,6 +139,13 @@ def cpu_baseline(n_sample):
 
 ADJOINT = dict(lam=1.0, beta=2.0, eps=0.1, c3=1.0, n=2 ** 20, S=10_000, dt=1e-4, every=256, seed=0,
                alpha=(0.1, 0.5, 0.9))
+# VALU instructions of one particle-step of forward + reverse sweep with four
+# seed vectors and checkpoints every 256 steps: the forward step (79, as the
+# fine propagator), the reverse sweep's two replays of it (2 x 79) and the
+# reverse recursion (the step's Jacobian and parameter derivatives, 29, and
+# per seed vector four gradient updates and the 2 x 2 transposed Jacobian
+# product, 10, for four vectors 40: 69): 306
+ADJ_OPS_PER_STEP = 79 + 2 * 79 + 69
 
 
 def adjoint_measure(torch, pr):
@@ -209,7 +216,9 @@ def adjoint_measure(torch, pr):
     return dict(workload="adjoint of the 2-D SDE (lambda=1, beta=2, eps=0.1), P=2^20 FP64, 1e4 steps of dt=1e-4, "
                          "checkpoints every 256 steps, observables mean X_T^2 and quantiles 0.1/0.5/0.9, "
                          "4x4 Jacobian w.r.t. (lambda, eps, beta, c3) in one reverse sweep",
-                fwd_plus_adjoint_particle_steps_per_s=n * S / total, forward_ckpt_s=t_fwd, observables_s=t_obs,
+                fwd_plus_adjoint_particle_steps_per_s=n * S / total,
+                valu_frac=ADJ_OPS_PER_STEP * (n * S / total) / VALU_PEAK, ops_per_particle_step=ADJ_OPS_PER_STEP,
+                forward_ckpt_s=t_fwd, observables_s=t_obs,
                 reverse_s=t_adj, plain_forward_s=t_plain, reverse_over_forward=t_adj / t_fwd,
                 ratio_to_8_crn_fd_forwards=total / (8 * t_plain),
                 ckpt_every_8=every8,

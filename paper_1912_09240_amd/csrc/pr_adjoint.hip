@@ -125,14 +125,20 @@ adjoint_kernel(const double *__restrict__ ckpt, int n_ckpt, int every, int64_t n
                         em_step_d1(xv, yv, ec, tab, key, inst, (uint32_t)m, (uint32_t)p);
                 }
             }
-            // level 2: each sub-segment, last first
+            // level 2: each sub-segment, last first; the start of the next
+            // one is loaded while this one is replayed
+            const double *tj = every > AD_SUB ? sub + (2 * (int64_t)(nsub - 1)) * n : ckpt + (2 * (int64_t)seg) * n;
+            double nxs = tj[p], nys = tj[n + p];
             for (int j = nsub - 1; j >= 0; --j) {
                 const int64_t ms = m0 + (int64_t)j * AD_SUB;
                 const int L = (int)((m1 - ms) < AD_SUB ? (m1 - ms) : AD_SUB);
                 double tx[AD_SUB + 1], ty[AD_SUB + 1];
-                const double *t0 = every > AD_SUB ? sub + (2 * (int64_t)j) * n : ckpt + (2 * (int64_t)seg) * n;
-                tx[0] = t0[p];
-                ty[0] = t0[n + p];
+                tx[0] = nxs;
+                ty[0] = nys;
+                if (j > 0) {  // only with every > AD_SUB (one tape otherwise)
+                    nxs = sub[(2 * (int64_t)(j - 1)) * n + p];
+                    nys = sub[(2 * (int64_t)(j - 1) + 1) * n + p];
+                }
 #pragma unroll
                 for (int i = 0; i < AD_SUB; ++i) {
                     double a = tx[i], b = ty[i];

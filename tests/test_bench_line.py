@@ -32,6 +32,7 @@ def _detail():
                                  max_over_slices=[2.3456789e-3 / (i + 1) for i in range(it)]),
              serial_fine_s=0.33123456, create_s=1.2345678)
     d["adjoint"] = dict(workload="w" * 300, fwd_plus_adjoint_particle_steps_per_s=1.0123456e11,
+                        valu_frac=0.8312345, ops_per_particle_step=306,
                         forward_ckpt_s=0.0251234567, observables_s=0.00123456, reverse_s=0.0791234567,
                         plain_forward_s=0.024123456, reverse_over_forward=3.1234567,
                         ratio_to_8_crn_fd_forwards=0.51234567, jacobian=[[1.0] * 4] * 4, observables=[1.0] * 4,
