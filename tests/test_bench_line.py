@@ -44,7 +44,7 @@ def _detail():
                         sweep_ms_batched=455.123456, sweep_ms_per_instance=1031.123456,
                         particle_steps_per_s_graph=3.9712345e11, particle_steps_per_s_per_instance=1.79e11,
                         speedup_vs_per_instance=2.2123456, create_s=5.123456, same_quantile_error=True,
-                        iterations_compared=4)
+                        iterations_compared=4, sweep_floor_ms=371.123456, sweep_floor_frac_graph=0.8212345)
     d["cpu_baseline"] = dict(value=3.41234567e8, unit="particle-steps/s", cores=16, kind="oracle",
                              sample="s" * 330, cpu_model="AMD EPYC 9575F 64-Core Processor", nproc=256,
                              one_thread=dict(value=2.41234567e7, sample="t" * 60))

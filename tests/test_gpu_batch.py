@@ -191,3 +191,45 @@ def test_batch_equals_single_instance_handles_bitwise(torch_dev):
                 assert np.array_equal(b, y.cpu().numpy()), (iid, t)
         finally:
             pr.pr_parareal_destroy(hs)
+
+
+def test_batched_workload_full_size_first_iteration(torch_dev):
+    """The batched workload at its full size (256 instances drawn from seed
+    0, 200 cells, 100 levels, creation as the benchmark does it): after one
+    iteration replayed from the graph, every instance's state at the end of
+    its first slice is the fine propagation of its initial ensemble over that
+    slice, bit for bit (Sec. 3.3.3), and the knots of that state are those of
+    the single-instance restriction of it."""
+    torch = torch_dev
+    _say("batched workload full size")
+    draw = torch.empty((256, 4), dtype=torch.float64, device="cuda")
+    pr.pr_draw_instances(0, 256, draw)
+    d = draw.cpu().numpy()
+    sdes, scheds, ns = [], [], []
+    for eps, lam, lg, K in d:
+        dt = eps / 20
+        S = int(round(2.0 / dt))
+        sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=2.0))
+        scheds.append(pr.Schedule(S, int(K), 2.0 / S))
+        ns.append(2 ** int(lg))
+    h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=200, n_q=100), 0, flags=pr.PR_AUTOTUNE)
+    try:
+        pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_GRAPH)
+        for i in range(256):
+            n = ns[i]
+            x = torch.empty(n, dtype=torch.float64, device="cuda")
+            y = torch.empty(n, dtype=torch.float64, device="cuda")
+            pr.pr_init_ensemble(sdes[i], 0, i, n, x, y)
+            pr.pr_fine_propagate(sdes[i], scheds[i], 0, i, n, 0, 1, x, y)
+            xb = torch.empty(n, dtype=torch.float64, device="cuda")
+            yb = torch.empty(n, dtype=torch.float64, device="cuda")
+            qb = torch.empty(101, dtype=torch.float64, device="cuda")
+            pr.pr_parareal_batch_state(h, i, 1, x=xb, y=yb, q=qb)
+            q = torch.empty(101, dtype=torch.float64, device="cuda")
+            ws = torch.empty(pr.pr_restrict_workspace_size(n, 1), dtype=torch.uint8, device="cuda")
+            pr.pr_restrict_quantiles(x, pr.PR_F64, n, 1, 100, q, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(xb, x) and torch.equal(yb, y), i
+            assert torch.equal(qb, q), i
+    finally:
+        pr.pr_parareal_batch_destroy(h)

@@ -127,6 +127,39 @@ def test_fine_large_workload_sampled(torch_dev):
         assert np.abs(yg - yr[0]).max() < 1e-12 * max(1.0, np.abs(yr).max()), k
 
 
+def test_fine_high_dim_workload_sampled(torch_dev):
+    """The fast part in R^32 at its full size and launch (P = 2^20, all 32
+    slices of 5e4 steps of dt = 1e-4 in one launch, FP64), each slice from
+    its own start state, against the oracle on 8 particles of every slice
+    (the last 8 of the last slice included)."""
+    torch = torch_dev
+    n, K, d, S, dt, eps = 2 ** 20, 32, 32, 50_000, 1e-4, 0.01
+    _say(f"fine d=32 full size n={n} K={K} S={S}")
+    a_np = OP.coupling(0, 0, d)
+    so = OP.Sde(lam=1.0, eps=eps, beta=2.0, d=d, a=a_np)
+    a = torch.from_numpy(a_np).cuda()
+    sde = pr.Sde(lam=1.0, eps=eps, beta=2.0, d=d, a=a)
+    x0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    y0 = torch.empty((d, n), dtype=torch.float64, device="cuda")
+    pr.pr_init_ensemble(sde, 0, 0, n, x0, y0)
+    shift = 0.01 * torch.arange(K, dtype=torch.float64, device="cuda")
+    x = (x0.unsqueeze(0) + shift[:, None]).contiguous()
+    y = (y0.unsqueeze(0) - shift[:, None, None]).contiguous()
+    pr.pr_fine_propagate(sde, pr.Schedule(S, K, dt), 0, 0, n, 0, K, x, y)
+    _sync(torch)
+    x0h, y0h = OP.init_ensemble(so, 0, 0, n)
+    assert np.abs(x0.cpu().numpy() - x0h).max() < 1e-14
+    b = OI.slice_bounds(S, K)
+    for k in range(K):
+        p0 = n - 8 if k == K - 1 else (k * 32_749) % (n - 8)
+        xg = x[k, p0:p0 + 8].cpu().numpy()
+        yg = y[k, :, p0:p0 + 8].cpu().numpy()
+        xr, yr = OP.em_propagate(so, 0, 0, x0h[p0:p0 + 8] + 0.01 * k, y0h[:, p0:p0 + 8] - 0.01 * k, b[k], b[k + 1],
+                                 dt, p0=p0)
+        assert np.abs(xg - xr).max() < 1e-12 * max(1.0, np.abs(xr).max()), k
+        assert np.abs(yg - yr).max() < 1e-12 * max(1.0, np.abs(yr).max()), k
+
+
 def test_fine_subrange_and_in_place(torch_dev):
     """Slices [2, 4) of a 5-slice schedule on their own give the same numbers
     as inside a full launch (counter-based noise keyed by the global step)."""
