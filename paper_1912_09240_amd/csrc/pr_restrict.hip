@@ -429,8 +429,9 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 //   ss_splitters    splitter b = the mean over the runs of their b-th
 //                   quantile value (non-decreasing in b, as every run's
 //                   quantiles are);
-//   ss_count        bucket histogram of every tile (the moments and the cell
-//                   histogram fused into this first read of the values);
+//   ss_count        bucket histogram of every tile and the bucket of every
+//                   key (one byte; the moments and the cell histogram fused
+//                   into this first read of the values);
 //   rs_rowscan      tile offsets and bucket totals, as for a radix pass;
 //   ss_scatter      stable scatter of (key, particle) into the buckets, so
 //                   that inside a bucket the particles keep their order;
@@ -513,7 +514,7 @@ __global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict_
 
 __global__ void __launch_bounds__(RS_THREADS)
 ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, SortLayout L,
-         uint32_t *__restrict__ counts, double *__restrict__ mom_part, HistArgs ha) {
+         uint32_t *__restrict__ counts, double *__restrict__ mom_part, HistArgs ha, uint8_t *__restrict__ bucket) {
     constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
     __shared__ uint32_t h[RS_WAVES][2][RS_RADIX];
     __shared__ double wsum[RS_WAVES][4];
@@ -539,6 +540,12 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
     uint32_t bk[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) bk[i] = ss_bucket_of(key_of(in[i]), sp);
+    // every key's bucket for the scatter, one byte each
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const int64_t idx = t0 + i * 64 + lane;
+        if (idx < T.n) bucket[T.base + idx] = (uint8_t)bk[i];
+    }
     double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -593,7 +600,7 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
 // Stable scatter of (key, particle) into the buckets: the arithmetic of
 // rs_scatter's first pass with the bucket in place of the digit.
 __global__ void __launch_bounds__(RS_THREADS)
-ss_scatter(const double *__restrict__ src, const uint64_t *__restrict__ split, uint64_t *__restrict__ keys_out,
+ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, uint64_t *__restrict__ keys_out,
            uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
            const uint32_t *__restrict__ totals, SortLayout L, uint32_t *__restrict__ bstart) {
     constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
@@ -603,15 +610,13 @@ ss_scatter(const double *__restrict__ src, const uint64_t *__restrict__ split, u
     __shared__ uint32_t wtot[RS_WAVES];
     __shared__ uint64_t stage[TILE];
     __shared__ uint8_t sdig[TILE];
-    __shared__ uint64_t sp[SS_B];
 
     const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int i = tid; i < SS_B; i += RS_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
     for (int i = lane; i < RS_RADIX; i += 64) wcnt[wave][i] = 0;
-    __syncthreads();
+    wave_sync();
 
     uint64_t key[ITEMS];
     uint32_t dig[ITEMS], rnk[ITEMS];
@@ -620,12 +625,12 @@ ss_scatter(const double *__restrict__ src, const uint64_t *__restrict__ split, u
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = t0 + i * 64 + lane;
         in[i] = idx < T.n ? src[T.base + idx] : 0.0;
+        dig[i] = idx < T.n ? (uint32_t)bucket[T.base + idx] : 0u;
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const bool valid = t0 + i * 64 + lane < T.n;
         key[i] = valid ? key_of(in[i]) : 0ull;
-        dig[i] = valid ? ss_bucket_of(key[i], sp) : 0u;
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -806,16 +811,24 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         if (tid == 0) *flag = 1;
         return;
     }
+    // every slot first (the atomics of all items in flight together), then
+    // the stores
+    uint16_t slot[SS_IT];
 #pragma unroll
     for (int i = 0; i < SS_IT; ++i) {
         const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        slot[i] = 0xFFFF;
         if (idx < size) {
             const uint32_t sh = 16 * (sub[i] & 1);
-            const uint32_t slot = (atomicAdd(&cursor[sub[i] >> 1], 1u << sh) >> sh) & 0xFFFFu;
-            sk[slot] = k[i];
-            spos[slot] = (uint16_t)idx;
+            slot[i] = (uint16_t)((atomicAdd(&cursor[sub[i] >> 1], 1u << sh) >> sh) & 0xFFFFu);
         }
     }
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i)
+        if (slot[i] != 0xFFFF) {
+            sk[slot[i]] = k[i];
+            spos[slot[i]] = (uint16_t)((uint32_t)tid + (uint32_t)i * SS_BT);
+        }
     __syncthreads();
     // place: the keys of the sub-bucket before this one by (key, position in
     // the bucket's input, which is the particles' order)
@@ -826,10 +839,20 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         fin[i] = 0xFFFF;
         if (idx < size) {
             const uint32_t a = sstart[sub[i]], e = (cursor[sub[i] >> 1] >> (16 * (sub[i] & 1))) & 0xFFFFu;
+            // four entries per step, their LDS loads in flight together
             uint32_t r = a;
-            for (uint32_t j = a; j < e; ++j) {
-                const uint64_t kj = sk[j];
-                r += (kj < k[i] || (kj == k[i] && spos[j] < idx)) ? 1u : 0u;
+            for (uint32_t j = a; j < e; j += 4) {
+                uint64_t kj[4];
+                uint16_t pj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t jj = j + u < e ? j + u : a;
+                    kj[u] = sk[jj];
+                    pj[u] = spos[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    r += (j + u < e && (kj[u] < k[i] || (kj[u] == k[i] && pj[u] < idx))) ? 1u : 0u;
             }
             fin[i] = (uint16_t)r;
         }
@@ -1567,12 +1590,15 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
             PR_LAUNCHED();
             hipLaunchKernelGGL(ss_splitters, dim3((unsigned)L.nseg), dim3(SS_B), 0, st, (const uint64_t *)runq, split);
             PR_LAUNCHED();
+            // the bucket of every key, one byte each, in the first payload
+            // buffer (free until the bucket sort writes the permutation)
+            uint8_t *bucket = (uint8_t *)vals[0];
             hipLaunchKernelGGL(ss_count, grid, dim3(RS_THREADS), cell_lds, st, (const double *)x,
-                               (const uint64_t *)split, L, counts, mom ? mom_part : nullptr, ha);
+                               (const uint64_t *)split, L, counts, mom ? mom_part : nullptr, ha, bucket);
             PR_LAUNCHED();
             hipLaunchKernelGGL((rs_rowscan<false>), rows, dim3(256), 0, st, counts, totals, L);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(ss_scatter, grid, dim3(RS_THREADS), 0, st, (const double *)x, (const uint64_t *)split,
+            hipLaunchKernelGGL(ss_scatter, grid, dim3(RS_THREADS), 0, st, (const double *)x, (const uint8_t *)bucket,
                                (uint64_t *)keys[1], vals[1], (const uint32_t *)counts, (const uint32_t *)totals, L,
                                bstart);
             PR_LAUNCHED();
