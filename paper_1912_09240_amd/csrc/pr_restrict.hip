@@ -433,14 +433,14 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 //                   key (one byte; the moments and the cell histogram fused
 //                   into this first read of the values);
 //   rs_rowscan      tile offsets and bucket totals, as for a radix pass;
-//   ss_scatter      stable scatter of (key, particle) into the buckets, so
-//                   that inside a bucket the particles keep their order;
+//   ss_scatter      scatter of (key, particle) into the buckets (in any
+//                   order inside a bucket: slots from LDS atomics);
 //   ss_bucket_sort  one block per bucket: the keys go to value sub-buckets
 //                   (linear in the value between the bucket's bounds, which
 //                   keeps the order), every key counts the keys of its
-//                   sub-bucket that precede it by (key, position in the
-//                   bucket), and the bucket is written out in order with its
-//                   permutation.
+//                   sub-bucket that precede it by (key, particle), the
+//                   particles read only for equal keys, and the bucket is
+//                   written out in order with its permutation.
 // A bucket above SS_CAP keys or a sub-bucket above SS_SUBMAX raises the flag
 // that runs the complete radix sort behind it.  Compared with four radix
 // passes and the fix-up this moves about half the bytes per key.
@@ -449,13 +449,13 @@ constexpr int SS_B = 256;
 constexpr int SS_RUNS = 16;
 constexpr int SS_RUN = 1024;
 constexpr int SS_BT = 512;                  // threads of a bucket block
-constexpr int SS_IT = 15;                   // keys per thread of a bucket block
-constexpr int SS_CAP = SS_BT * SS_IT;       // 7680: two bucket blocks share a CU's LDS
-constexpr int SS_SUB = 1024;
+constexpr int SS_IT = 14;                   // keys per thread of a bucket block
+constexpr int SS_CAP = SS_BT * SS_IT;       // 7168: two bucket blocks share a CU's LDS
+constexpr int SS_SUB = 2048;
 constexpr int SS_SUBMAX = 512;
 constexpr int64_t SS_MIN_N = (int64_t)1 << 16;
 static_assert(SS_B == RS_RADIX, "buckets take the place of a radix pass's digits");
-static_assert(SS_SUB == 2 * SS_BT, "two sub-bucket counts per thread");
+static_assert(SS_SUB == 4 * SS_BT, "four sub-bucket counts per thread");
 
 // Bucket of a key: the number of splitters sp[1..SS_B-1] at or below it.
 __device__ __forceinline__ uint32_t ss_bucket_of(uint64_t key, const uint64_t *sp) {
@@ -597,15 +597,16 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
             if (cell_h[i]) atomicAdd(&ha.hist[(int64_t)T.seg * ha.cells + i], cell_h[i]);
 }
 
-// Stable scatter of (key, particle) into the buckets: the arithmetic of
-// rs_scatter's first pass with the bucket in place of the digit.
+// Scatter of (key, particle) into the buckets.  The order inside a bucket
+// is left to the block's LDS atomics: the bucket sort orders by (key,
+// particle) whatever order its input has.
 __global__ void __launch_bounds__(RS_THREADS)
 ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, uint64_t *__restrict__ keys_out,
            uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
            const uint32_t *__restrict__ totals, SortLayout L, uint32_t *__restrict__ bstart) {
     constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
-    __shared__ uint32_t wcnt[RS_WAVES][RS_RADIX];
-    __shared__ uint32_t wbase[RS_WAVES][RS_RADIX];
+    __shared__ uint32_t bcnt[RS_RADIX];
+    __shared__ uint32_t lstart[RS_RADIX];
     __shared__ uint32_t gdelta[RS_RADIX];
     __shared__ uint32_t wtot[RS_WAVES];
     __shared__ uint64_t stage[TILE];
@@ -614,69 +615,37 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
     const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int i = lane; i < RS_RADIX; i += 64) wcnt[wave][i] = 0;
-    wave_sync();
+    bcnt[tid] = 0;
+    __syncthreads();
 
-    uint64_t key[ITEMS];
-    uint32_t dig[ITEMS], rnk[ITEMS];
+    // bucket (low byte) and slot among the tile's keys of that bucket
+    uint32_t dr[ITEMS];
     double in[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const int64_t idx = t0 + i * 64 + lane;
         in[i] = idx < T.n ? src[T.base + idx] : 0.0;
-        dig[i] = idx < T.n ? (uint32_t)bucket[T.base + idx] : 0u;
+        dr[i] = idx < T.n ? (uint32_t)bucket[T.base + idx] : 0u;
     }
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const bool valid = t0 + i * 64 + lane < T.n;
-        key[i] = valid ? key_of(in[i]) : 0ull;
-    }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const bool valid = t0 + i * 64 + lane < T.n;
-        const uint32_t d = dig[i];
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
-        uint32_t base = 0;
-        if (valid) base = wcnt[wave][d];
-        rnk[i] = base + (uint32_t)__popcll(peers & lt);
-        wave_sync();
-        if (valid && lane == 63 - __clzll(peers)) wcnt[wave][d] = base + (uint32_t)__popcll(peers);
-        wave_sync();
-    }
+    for (int i = 0; i < ITEMS; ++i)
+        if (t0 + i * 64 + lane < T.n) dr[i] |= atomicAdd(&bcnt[dr[i]], 1u) << 8;
     __syncthreads();
     {
         const int d = tid;
-        uint32_t c[RS_WAVES], tot = 0;
-#pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) {
-            c[w] = wcnt[w][d];
-            tot += c[w];
-        }
-        const uint32_t lstart = block_exclusive_256(tot, wtot);
+        const uint32_t ls = block_exclusive_256(bcnt[d], wtot);
         const uint32_t dbase = block_exclusive_256(totals[(int64_t)T.seg * RS_RADIX + d], wtot);
-        uint32_t acc = lstart;
-#pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) {
-            wbase[w][d] = acc;
-            acc += c[w];
-        }
-        gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - lstart;
+        lstart[d] = ls;
+        gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - ls;
         if (T.blk == 0) bstart[(int64_t)T.seg * RS_RADIX + d] = dbase;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
         if (t0 + i * 64 + lane < T.n) {
-            const uint32_t j = wbase[wave][dig[i]] + rnk[i];
-            stage[j] = key[i];
-            sdig[j] = (uint8_t)dig[i];
+            const uint32_t j = lstart[dr[i] & 0xFFu] + (dr[i] >> 8);
+            stage[j] = key_of(in[i]);
+            sdig[j] = (uint8_t)dr[i];
         }
     __syncthreads();
     const int64_t rem = T.n - (int64_t)T.blk * TILE;
@@ -698,7 +667,7 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
     uint32_t *sv = (uint32_t *)stage;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i)
-        if (t0 + i * 64 + lane < T.n) sv[wbase[wave][dig[i]] + rnk[i]] = (uint32_t)(t0 + i * 64 + lane);
+        if (t0 + i * 64 + lane < T.n) sv[lstart[dr[i] & 0xFFu] + (dr[i] >> 8)] = (uint32_t)(t0 + i * 64 + lane);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -744,11 +713,14 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
     const int64_t base = (int64_t)s * L.n + start;
     for (int i = tid; i < SS_SUB / 2; i += SS_BT) cursor[i] = 0;
     if (tid == 0) too_big = 0;
+    // keys and their particles, both read in order
     uint64_t k[SS_IT];
+    uint32_t v[SS_IT];
 #pragma unroll
     for (int i = 0; i < SS_IT; ++i) {
         const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
         k[i] = idx < size ? bkeys[base + idx] : ~0ull;
+        v[i] = idx < size ? bvals[base + idx] : 0u;
     }
     // bounds of the bucket's values: its splitters inside, its extremes at
     // the two ends of the ensemble
@@ -786,11 +758,14 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         }
     }
     __syncthreads();
-    // exclusive scan of the sub-bucket counts (two per thread), their maximum
+    // exclusive scan of the sub-bucket counts (four per thread), their maximum
     {
-        const uint32_t c0 = cursor[tid] & 0xFFFFu, c1 = cursor[tid] >> 16;
-        if (c0 > (uint32_t)SS_SUBMAX || c1 > (uint32_t)SS_SUBMAX) too_big = 1;
-        const uint32_t c = c0 + c1;
+        const uint32_t w0 = cursor[2 * tid], w1 = cursor[2 * tid + 1];
+        const uint32_t c0 = w0 & 0xFFFFu, c1 = w0 >> 16, c2 = w1 & 0xFFFFu, c3 = w1 >> 16;
+        if (c0 > (uint32_t)SS_SUBMAX || c1 > (uint32_t)SS_SUBMAX || c2 > (uint32_t)SS_SUBMAX ||
+            c3 > (uint32_t)SS_SUBMAX)
+            too_big = 1;
+        const uint32_t c = c0 + c1 + c2 + c3;
         const int lane = tid & 63, wave = tid >> 6;
         uint32_t inc = c;
         for (int off = 1; off < 64; off <<= 1) {
@@ -801,10 +776,13 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         __syncthreads();
         uint32_t pre = 0;
         for (int w = 0; w < wave; ++w) pre += red32[w];
-        const uint32_t e0 = pre + inc - c;
-        sstart[2 * tid] = (uint16_t)e0;
-        sstart[2 * tid + 1] = (uint16_t)(e0 + c0);
-        cursor[tid] = e0 | ((e0 + c0) << 16);
+        const uint32_t e0 = pre + inc - c, e1 = e0 + c0, e2 = e1 + c1, e3 = e2 + c2;
+        sstart[4 * tid] = (uint16_t)e0;
+        sstart[4 * tid + 1] = (uint16_t)e1;
+        sstart[4 * tid + 2] = (uint16_t)e2;
+        sstart[4 * tid + 3] = (uint16_t)e3;
+        cursor[2 * tid] = e0 | (e1 << 16);
+        cursor[2 * tid + 1] = e2 | (e3 << 16);
         __syncthreads();
     }
     if (too_big) {
@@ -830,8 +808,7 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
             spos[slot[i]] = (uint16_t)((uint32_t)tid + (uint32_t)i * SS_BT);
         }
     __syncthreads();
-    // place: the keys of the sub-bucket before this one by (key, position in
-    // the bucket's input, which is the particles' order)
+    // place: the keys of the sub-bucket before this one by (key, particle)
     uint16_t fin[SS_IT];
 #pragma unroll
     for (int i = 0; i < SS_IT; ++i) {
@@ -839,50 +816,58 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         fin[i] = 0xFFFF;
         if (idx < size) {
             const uint32_t a = sstart[sub[i]], e = (cursor[sub[i] >> 1] >> (16 * (sub[i] & 1))) & 0xFFFFu;
-            // four entries per step, their LDS loads in flight together
+            const uint32_t me = slot[i];
+            // four entries per step, their LDS loads in flight together; the
+            // steps past the end read the key's own slot, which never counts.
+            // Positions are read only for equal keys in other slots.
             uint32_t r = a;
             for (uint32_t j = a; j < e; j += 4) {
                 uint64_t kj[4];
-                uint16_t pj[4];
+                uint32_t jj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t jj = j + u < e ? j + u : a;
-                    kj[u] = sk[jj];
-                    pj[u] = spos[jj];
+                    jj[u] = j + u < e ? j + u : me;
+                    kj[u] = sk[jj[u]];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    r += (j + u < e && (kj[u] < k[i] || (kj[u] == k[i] && pj[u] < idx))) ? 1u : 0u;
+                for (int u = 0; u < 4; ++u) {
+                    if (kj[u] < k[i]) ++r;
+                    else if (kj[u] == k[i] && jj[u] != me && bvals[base + spos[jj[u]]] < v[i]) ++r;
+                }
             }
             fin[i] = (uint16_t)r;
         }
     }
+    // the keys, then their particles, pass through LDS to their final
+    // slots and leave in order (the particles in the keys' own array)
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < SS_IT; ++i)
-        if (fin[i] != 0xFFFF) {
-            sk[fin[i]] = k[i];
-            spos[fin[i]] = (uint16_t)((uint32_t)tid + (uint32_t)i * SS_BT);
-        }
+        if (fin[i] != 0xFFFF) sk[fin[i]] = k[i];
     __syncthreads();
-    // the particles of all output slots are gathered first (one load per
-    // slot, all in flight together), then every output is stored
-    uint64_t ok[SS_IT];
-    uint32_t op[SS_IT];
-#pragma unroll
-    for (int i = 0; i < SS_IT; ++i) {
-        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
-        ok[i] = idx < size ? sk[idx] : 0ull;
-        op[i] = idx < size ? bvals[base + spos[idx]] : 0u;
-    }
 #pragma unroll
     for (int i = 0; i < SS_IT; ++i) {
         const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
         if (idx < size) {
-            keys_out[base + idx] = ok[i];
-            if (xs_out) xs_out[base + idx] = value_of(ok[i]);
-            if (perm_out) perm_out[base + idx] = op[i];
-            if (rank_out) rank_out[(int64_t)s * L.n + op[i]] = start + idx;
+            const uint64_t ok = sk[idx];
+            keys_out[base + idx] = ok;
+            if (xs_out) xs_out[base + idx] = value_of(ok);
+        }
+    }
+    if (!perm_out && !rank_out) return;
+    __syncthreads();
+    uint32_t *sv = reinterpret_cast<uint32_t *>(sk);
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i)
+        if (fin[i] != 0xFFFF) sv[fin[i]] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SS_IT; ++i) {
+        const uint32_t idx = (uint32_t)tid + (uint32_t)i * SS_BT;
+        if (idx < size) {
+            const uint32_t op = sv[idx];
+            if (perm_out) perm_out[base + idx] = op;
+            if (rank_out) rank_out[(int64_t)s * L.n + op] = start + idx;
         }
     }
 }

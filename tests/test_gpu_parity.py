@@ -356,14 +356,17 @@ def _splitter_case(case, k, n):
         x[:, 5::991] = -np.inf
         x[:, 7::89] = -0.0
         x[:, 11::97] = 0.0
+    elif case == 5:  # a few copies of most values, spread over every bucket
+        x = np.round(rng.normal(0.0, 1.0, (k, n)) * 8000.0) / 8000.0
     return np.ascontiguousarray(x)
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_restrict_splitter_cases(torch_dev, case):
     """Ensembles of 2^17 particles (sorted by splitters and buckets where
     every bucket fits, by the complete radix sort otherwise): smooth values,
-    all equal, a far outlier, long runs of ties, infinities and signed zeros.
+    all equal, a far outlier, long runs of ties, infinities and signed zeros,
+    a few copies of most values.
     Every output bit for bit against the oracle's stable sort."""
     torch = torch_dev
     k, n = 2, 2 ** 17
