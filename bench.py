@@ -237,7 +237,9 @@ def batched_measure(torch, pr):
     instance by instance (the plain launch pattern).  Their knots of every
     state of every instance are then compared bit for bit, so the sweep times
     are compared at the same quantile error.  Device time per iteration from
-    HIP events."""
+    HIP events, and the device time of all four iterations of each handle
+    (to the final iteration; the graph capture is host work before the first
+    timed replay)."""
     b = BATCH
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
     with torch.cuda.stream(stream):
@@ -268,7 +270,7 @@ def batched_measure(torch, pr):
         t_create = time.perf_counter() - t0
         try:
             info = pr.pr_parareal_batch_info(h)
-            pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_GRAPH)  # capture + warm-up
+            ms_first = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_GRAPH, timed=True)  # captures first
             ms_graph = pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH, timed=True) / 2
             ms_batched = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED, timed=True)
             qa = knots(h)
@@ -276,7 +278,7 @@ def batched_measure(torch, pr):
             pr.pr_parareal_batch_destroy(h)
         h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, b["seed"], flags=pr.PR_AUTOTUNE)
         try:
-            pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_PER_INSTANCE)
+            ms_plain3 = pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_PER_INSTANCE, timed=True)
             ms_plain = pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_PER_INSTANCE, timed=True)
             qb = knots(h)
         finally:
@@ -292,6 +294,8 @@ def batched_measure(torch, pr):
                 particle_steps_per_s_per_instance=w / (ms_plain / 1e3),
                 speedup_vs_per_instance=ms_plain / ms_graph, create_s=t_create,
                 same_quantile_error=same, iterations_compared=4,
+                to_final_ms_batched=ms_first + 2 * ms_graph + ms_batched,
+                to_final_ms_per_instance=ms_plain3 + ms_plain,
                 # the sweep against its floor: the fine particle-steps at the
                 # VALU issue peak (the restriction, chains and matching count
                 # as overhead here)
@@ -710,6 +714,8 @@ def summary_line(d, args, config):
                            speedup_vs_per_instance=_sig(b["speedup_vs_per_instance"]),
                            particle_steps_per_s_graph=_sig(b["particle_steps_per_s_graph"]),
                            same_quantile_error=b["same_quantile_error"], iterations_compared=b["iterations_compared"],
+                           to_final_ms_batched=_sig(b.get("to_final_ms_batched")),
+                           to_final_ms_per_instance=_sig(b.get("to_final_ms_per_instance")),
                            sweep_floor_frac_graph=_sig(b.get("sweep_floor_frac_graph")))
     line["sweep_roofline"] = dict(floor_ms=_sig(d["sweep_roofline"]["floor_ms"]),
                                   frac=_sig(d["sweep_roofline"]["frac"]))

@@ -448,14 +448,14 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 constexpr int SS_B = 256;
 constexpr int SS_RUNS = 16;
 constexpr int SS_RUN = 1024;
-constexpr int SS_BT = 512;                  // threads of a bucket block
-constexpr int SS_IT = 14;                   // keys per thread of a bucket block
+constexpr int SS_BT = 1024;                 // threads of a bucket block
+constexpr int SS_IT = 7;                    // keys per thread of a bucket block
 constexpr int SS_CAP = SS_BT * SS_IT;       // 7168: two bucket blocks share a CU's LDS
 constexpr int SS_SUB = 2048;
 constexpr int SS_SUBMAX = 512;
 constexpr int64_t SS_MIN_N = (int64_t)1 << 16;
 static_assert(SS_B == RS_RADIX, "buckets take the place of a radix pass's digits");
-static_assert(SS_SUB == 4 * SS_BT, "four sub-bucket counts per thread");
+static_assert(SS_SUB == 2 * SS_BT, "two sub-bucket counts per thread");
 
 // Bucket of a key: the number of splitters sp[1..SS_B-1] at or below it.
 __device__ __forceinline__ uint32_t ss_bucket_of(uint64_t key, const uint64_t *sp) {
@@ -512,21 +512,27 @@ __global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict_
     split[(int64_t)s * SS_B + b] = b == 0 ? 0ull : key_of(acc);
 }
 
-__global__ void __launch_bounds__(RS_THREADS)
+// The tiles of the radix passes (RS_THREADS x RS_ITEMS keys) are taken by
+// twice the threads with half the keys each in the splitter sort's
+// per-key passes.
+constexpr int SC_THREADS = 2 * RS_THREADS;
+constexpr int SC_WAVES = SC_THREADS / 64;
+
+__global__ void __launch_bounds__(SC_THREADS)
 ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, SortLayout L,
          uint32_t *__restrict__ counts, double *__restrict__ mom_part, HistArgs ha, uint8_t *__restrict__ bucket) {
-    constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
-    __shared__ uint32_t h[RS_WAVES][2][RS_RADIX];
-    __shared__ double wsum[RS_WAVES][4];
+    constexpr int TILE = RS_THREADS * RS_ITEMS, ITEMS = TILE / SC_THREADS, WAVE_KEYS = 64 * ITEMS;
+    __shared__ uint32_t h[SC_WAVES][2][RS_RADIX];
+    __shared__ double wsum[SC_WAVES][4];
     __shared__ uint64_t sp[SS_B];
     extern __shared__ uint32_t cell_h[];
     const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < RS_WAVES * 2 * RS_RADIX; i += RS_THREADS) (&h[0][0][0])[i] = 0;
-    for (int i = tid; i < SS_B; i += RS_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
+    for (int i = tid; i < SC_WAVES * 2 * RS_RADIX; i += SC_THREADS) (&h[0][0][0])[i] = 0;
+    for (int i = tid; i < SS_B; i += SC_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
     const bool do_hist = ha.hist != nullptr;
     if (do_hist)
-        for (int i = tid; i < ha.cells; i += RS_THREADS) cell_h[i] = 0;
+        for (int i = tid; i < ha.cells; i += SC_THREADS) cell_h[i] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     double in[ITEMS];
@@ -580,42 +586,59 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
         }
     }
     __syncthreads();
-    {
+    if (tid < RS_RADIX) {
         const int d = tid;
         uint32_t c = 0;
 #pragma unroll
-        for (int w = 0; w < RS_WAVES; ++w) c += h[w][0][d] + h[w][1][d];
+        for (int w = 0; w < SC_WAVES; ++w) c += h[w][0][d] + h[w][1][d];
         counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] = c;
     }
     if (mom_part != nullptr && tid < 4) {
         double t = 0;
-        for (int w = 0; w < RS_WAVES; ++w) t += wsum[w][tid];
+        for (int w = 0; w < SC_WAVES; ++w) t += wsum[w][tid];
         mom_part[(T.tile0 + T.blk) * 4 + tid] = t;
     }
     if (do_hist)
-        for (int i = tid; i < ha.cells; i += RS_THREADS)
+        for (int i = tid; i < ha.cells; i += SC_THREADS)
             if (cell_h[i]) atomicAdd(&ha.hist[(int64_t)T.seg * ha.cells + i], cell_h[i]);
+}
+
+// Exclusive prefix of one value per thread over a block of NT threads.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *wtot) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wtot[w];
+    __syncthreads();
+    return pre + inc - v;
 }
 
 // Scatter of (key, particle) into the buckets.  The order inside a bucket
 // is left to the block's LDS atomics: the bucket sort orders by (key,
 // particle) whatever order its input has.
-__global__ void __launch_bounds__(RS_THREADS)
+__global__ void __launch_bounds__(SC_THREADS)
 ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, uint64_t *__restrict__ keys_out,
            uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
            const uint32_t *__restrict__ totals, SortLayout L, uint32_t *__restrict__ bstart) {
-    constexpr int ITEMS = RS_ITEMS, WAVE_KEYS = 64 * ITEMS, TILE = RS_THREADS * ITEMS;
+    constexpr int TILE = RS_THREADS * RS_ITEMS, ITEMS = TILE / SC_THREADS, WAVE_KEYS = 64 * ITEMS;
     __shared__ uint32_t bcnt[RS_RADIX];
     __shared__ uint32_t lstart[RS_RADIX];
     __shared__ uint32_t gdelta[RS_RADIX];
-    __shared__ uint32_t wtot[RS_WAVES];
+    __shared__ uint32_t wtot[SC_THREADS / 64];
     __shared__ uint64_t stage[TILE];
     __shared__ uint8_t sdig[TILE];
 
     const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
-    bcnt[tid] = 0;
+    if (tid < RS_RADIX) bcnt[tid] = 0;
     __syncthreads();
 
     // bucket (low byte) and slot among the tile's keys of that bucket
@@ -632,12 +655,16 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
         if (t0 + i * 64 + lane < T.n) dr[i] |= atomicAdd(&bcnt[dr[i]], 1u) << 8;
     __syncthreads();
     {
-        const int d = tid;
-        const uint32_t ls = block_exclusive_256(bcnt[d], wtot);
-        const uint32_t dbase = block_exclusive_256(totals[(int64_t)T.seg * RS_RADIX + d], wtot);
-        lstart[d] = ls;
-        gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - ls;
-        if (T.blk == 0) bstart[(int64_t)T.seg * RS_RADIX + d] = dbase;
+        // one thread per bucket; the other half adds zeros to the scans
+        const int d = tid & (RS_RADIX - 1);
+        const bool own = tid < RS_RADIX;
+        const uint32_t ls = block_exclusive<SC_THREADS>(own ? bcnt[d] : 0u, wtot);
+        const uint32_t dbase = block_exclusive<SC_THREADS>(own ? totals[(int64_t)T.seg * RS_RADIX + d] : 0u, wtot);
+        if (own) {
+            lstart[d] = ls;
+            gdelta[d] = dbase + counts[T.tile0 * RS_RADIX + (int64_t)d * T.nblk + T.blk] - ls;
+            if (T.blk == 0) bstart[(int64_t)T.seg * RS_RADIX + d] = dbase;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -653,7 +680,7 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
     uint32_t gpos[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int j = tid + r * RS_THREADS;
+        const int j = tid + r * SC_THREADS;
         gpos[r] = 0xFFFFFFFFu;
         if (j < tile_n) {
             const uint32_t g = (uint32_t)j + gdelta[sdig[j]];
@@ -671,7 +698,7 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int j = tid + r * RS_THREADS;
+        const int j = tid + r * SC_THREADS;
         if (j < tile_n && gpos[r] != 0xFFFFFFFFu) vals_out[T.base + gpos[r]] = sv[j];
     }
 }
@@ -758,14 +785,12 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         }
     }
     __syncthreads();
-    // exclusive scan of the sub-bucket counts (four per thread), their maximum
+    // exclusive scan of the sub-bucket counts (two per thread), their maximum
     {
-        const uint32_t w0 = cursor[2 * tid], w1 = cursor[2 * tid + 1];
-        const uint32_t c0 = w0 & 0xFFFFu, c1 = w0 >> 16, c2 = w1 & 0xFFFFu, c3 = w1 >> 16;
-        if (c0 > (uint32_t)SS_SUBMAX || c1 > (uint32_t)SS_SUBMAX || c2 > (uint32_t)SS_SUBMAX ||
-            c3 > (uint32_t)SS_SUBMAX)
-            too_big = 1;
-        const uint32_t c = c0 + c1 + c2 + c3;
+        const uint32_t w0 = cursor[tid];
+        const uint32_t c0 = w0 & 0xFFFFu, c1 = w0 >> 16;
+        if (c0 > (uint32_t)SS_SUBMAX || c1 > (uint32_t)SS_SUBMAX) too_big = 1;
+        const uint32_t c = c0 + c1;
         const int lane = tid & 63, wave = tid >> 6;
         uint32_t inc = c;
         for (int off = 1; off < 64; off <<= 1) {
@@ -776,13 +801,10 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         __syncthreads();
         uint32_t pre = 0;
         for (int w = 0; w < wave; ++w) pre += red32[w];
-        const uint32_t e0 = pre + inc - c, e1 = e0 + c0, e2 = e1 + c1, e3 = e2 + c2;
-        sstart[4 * tid] = (uint16_t)e0;
-        sstart[4 * tid + 1] = (uint16_t)e1;
-        sstart[4 * tid + 2] = (uint16_t)e2;
-        sstart[4 * tid + 3] = (uint16_t)e3;
-        cursor[2 * tid] = e0 | (e1 << 16);
-        cursor[2 * tid + 1] = e2 | (e3 << 16);
+        const uint32_t e0 = pre + inc - c, e1 = e0 + c0;
+        sstart[2 * tid] = (uint16_t)e0;
+        sstart[2 * tid + 1] = (uint16_t)e1;
+        cursor[tid] = e0 | (e1 << 16);
         __syncthreads();
     }
     if (too_big) {
@@ -1578,12 +1600,12 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
             // the bucket of every key, one byte each, in the first payload
             // buffer (free until the bucket sort writes the permutation)
             uint8_t *bucket = (uint8_t *)vals[0];
-            hipLaunchKernelGGL(ss_count, grid, dim3(RS_THREADS), cell_lds, st, (const double *)x,
+            hipLaunchKernelGGL(ss_count, grid, dim3(SC_THREADS), cell_lds, st, (const double *)x,
                                (const uint64_t *)split, L, counts, mom ? mom_part : nullptr, ha, bucket);
             PR_LAUNCHED();
             hipLaunchKernelGGL((rs_rowscan<false>), rows, dim3(256), 0, st, counts, totals, L);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(ss_scatter, grid, dim3(RS_THREADS), 0, st, (const double *)x, (const uint8_t *)bucket,
+            hipLaunchKernelGGL(ss_scatter, grid, dim3(SC_THREADS), 0, st, (const double *)x, (const uint8_t *)bucket,
                                (uint64_t *)keys[1], vals[1], (const uint32_t *)counts, (const uint32_t *)totals, L,
                                bstart);
             PR_LAUNCHED();

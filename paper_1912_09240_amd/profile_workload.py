@@ -140,8 +140,9 @@ def adjoint():
 def batch():
     """Batched form as the benchmark runs it: 256 instances drawn from seed
     0 (eps log-uniform in [1e-3, 1e-1], lambda in [0.5, 2], P in 2^12..2^18,
-    8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels); creation runs
-    the zeroth iteration, then one iteration in batched launches."""
+    8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels; the fine launch
+    shape autotuned); creation runs the zeroth iteration, then one iteration
+    in batched launches and two as graph replays."""
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         draw = torch.empty((256, 4), dtype=torch.float64, device="cuda")
@@ -153,11 +154,15 @@ def batch():
             sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=2.0))
             scheds.append(pr.Schedule(s_total, int(k), 2.0 / s_total))
             ns.append(2 ** int(lg))
-        h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=200, n_q=100), 0)
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, pr.Grid(n_cells=200, n_q=100), 0, flags=pr.PR_AUTOTUNE)
         try:
             print("batch: created", flush=True)
             pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED)
             torch.cuda.synchronize()
+            print("batch: batched iteration done", flush=True)
+            pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH)
+            torch.cuda.synchronize()
+            print("batch: graph iterations done", flush=True)
         finally:
             pr.pr_parareal_batch_destroy(h)
 
