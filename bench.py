@@ -61,7 +61,7 @@ FP64_FLOP_PER_STEP = 15
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
 # + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
 FINE_TRAFFIC_BYTES = (524410 * 2 + 1048576) * 1024
-FINE_SOURCES_SHA256 = "f88f7c4feb16bf764e30f104e5a429e56869fbc7b0d70a4878a48aff2c9cd825"
+FINE_SOURCES_SHA256 = "fc0b10586a5cda115f1bc7973b4b0b703f7a1c30fb04dd2ce34511e9e92ba987"
 FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
                 "pr_noise_tables.inc"]
 

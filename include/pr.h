@@ -311,7 +311,13 @@ int pr_parareal_destroy(void *h);
  * pr_parareal_batch_state copies the state of instance inst at time t.
  * pr_parareal_batch_info reports the tuned block size and particles per
  * thread, the number of fine work units and the fine particle-steps of one
- * iteration.  pr_draw_instances writes, for instances 0..count-1, the
+ * iteration.  pr_parareal_batch_knot_sorts returns the number of batched
+ * iterations whose new knots needed a sort of some new states (where the
+ * knots from the fine results' order could not isolate an order statistic),
+ * or -1 for h NULL; segments (host, may be NULL) receives how many
+ * ensembles those sorts covered (only the flagged ones are sorted).  The
+ * batched launch modes wait for their stream once per iteration to decide
+ * this.  pr_draw_instances writes, for instances 0..count-1, the
  * batched-workload draw of (eps, lambda, log2 n, slices) from the tag-3
  * block of each: eps = 10^(-3+2u0), lambda = 0.5+1.5u1, log2 n =
  * 12+floor(7u2), slices = 8+floor(57u3), u_k = (w_k + 1/2) 2^-32.
@@ -325,6 +331,7 @@ int pr_parareal_batch_iterate(void *h, int n_iter, int mode, double *ms_out, voi
 int pr_parareal_batch_state(void *h, int inst, int t, void *x, void *y, double *q, void *stream);
 int pr_parareal_batch_info(const void *h, int *tuned_block, int *tuned_ppt, int64_t *units,
                            int64_t *particle_steps);
+int pr_parareal_batch_knot_sorts(const void *h, int64_t *segments);
 int pr_parareal_batch_destroy(void *h);
 
 /*

@@ -20,7 +20,8 @@ __all__ = [
     "pr_parareal_knot_sorts", "pr_parareal_destroy", "pr_parareal_profile", "PR_F64", "PR_F32", "PR_REUSE_COARSE",
     "PR_SKIP_CONVERGED", "PR_PROFILE", "PHASES", "pr_fine_checkpoint", "pr_observables_workspace_size", "pr_observables",
     "pr_adjoint_workspace_size", "pr_fine_adjoint", "pr_draw_instances", "pr_parareal_batch_create",
-    "pr_parareal_batch_iterate", "pr_parareal_batch_state", "pr_parareal_batch_info", "pr_parareal_batch_destroy",
+    "pr_parareal_batch_iterate", "pr_parareal_batch_state", "pr_parareal_batch_info", "pr_parareal_batch_knot_sorts",
+    "pr_parareal_batch_destroy",
     "PR_AUTOTUNE", "PR_LAUNCH_BATCHED", "PR_LAUNCH_GRAPH", "PR_LAUNCH_PER_INSTANCE",
     "PR_J_ADD", "PR_J_MULT", "PR_J_ROT", "PR_J_QUANTILE", "PR_M_MARGINAL", "PR_M_REWEIGHT", "PR_M_RESAMPLE",
     "PR_M_RESAMPLE_DET", "pr_hist_workspace_size", "pr_hist_restrict", "pr_hist_jump_workspace_size", "pr_hist_jump",
@@ -167,6 +168,7 @@ _SIGS = {
     "pr_parareal_batch_state": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
     "pr_parareal_batch_info": (_c_int, [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_i64),
                                         ctypes.POINTER(_c_i64)]),
+    "pr_parareal_batch_knot_sorts": (_c_int, [_vp, ctypes.POINTER(_c_i64)]),
     "pr_parareal_batch_destroy": (_c_int, [_vp]),
     "pr_fine_adjoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64, _vp,
                                  _c_int, _vp, _vp, _c_int, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
@@ -429,6 +431,13 @@ def pr_parareal_batch_info(h):
     b, p, u, w = _c_int(), _c_int(), _c_i64(), _c_i64()
     _check(lib().pr_parareal_batch_info(h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(u), ctypes.byref(w)))
     return dict(block=b.value, ppt=p.value, units=u.value, particle_steps=w.value)
+
+
+def pr_parareal_batch_knot_sorts(h):
+    """(batched iterations whose new knots needed a sort, ensembles sorted)."""
+    segs = _c_i64(0)
+    n = lib().pr_parareal_batch_knot_sorts(h, ctypes.byref(segs))
+    return n, segs.value
 
 
 def pr_parareal_batch_destroy(h):

@@ -360,8 +360,15 @@ struct Batch {
     int64_t mk_chunks = 0, mk_groups = 0;
     int *flag = nullptr;
     int *flag_host = nullptr;  // pinned copy of flag
-    bool mk_ok = true;         // the matched-knot kernels serve this batch
-    int knot_sorts = 0;        // batched iterations whose new knots needed the sort
+    int *segflag = nullptr;    // one flag per fine-result ensemble
+    int *segflag_host = nullptr;
+    // the segment and tile tables of the ensembles whose knots need the sort
+    // (pinned host staging, device copies)
+    SortSeg *seg_sub_h = nullptr, *seg_sub = nullptr;
+    int *tile_sub_h = nullptr, *tile_sub = nullptr;
+    bool mk_ok = true;           // the matched-knot kernels serve this batch
+    int knot_sorts = 0;          // batched iterations whose new knots needed the sort
+    int64_t knot_sort_segs = 0;  // ensembles sorted by them
     int cur = 0, k = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -372,14 +379,16 @@ static void batch_free(Batch *b) {
     if (!b) return;
     void *ptrs[] = {b->inst, b->x[0], b->x[1], b->y[0], b->y[1], b->q, b->qn, b->qR, b->qf, b->qcs, b->rank,
                     b->ws, b->E, b->cu, b->chain, b->rho_a, b->units, b->counter, b->seg_f, b->tile_f, b->mseg,
-                    b->mtile, b->mk_seg, b->mk_gseg, b->flag};
+                    b->mtile, b->mk_seg, b->mk_gseg, b->flag, b->segflag, b->seg_sub, b->tile_sub};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &gx : b->graph)
         if (gx) (void)hipGraphExecDestroy(gx);
     for (auto &e : b->ev)
         if (e) (void)hipEventDestroy(e);
-    if (b->flag_host) (void)hipHostFree(b->flag_host);
+    void *pinned[] = {b->flag_host, b->segflag_host, b->seg_sub_h, b->tile_sub_h};
+    for (void *p : pinned)
+        if (p) (void)hipHostFree(p);
     delete b;
 }
 
@@ -527,15 +536,35 @@ static int autotune(Batch *b, hipStream_t st) {
 // matched-knot kernels raised the flag, the knots of the new states come from
 // a sort of them.  The host reads the flag once per iteration instead of
 // launching the sort guarded by it, whose empty launches cost more than the
-// wait.
+// wait.  Only the ensembles whose own flag is raised are sorted: their
+// segment entries (state offset, length, knot row) with tiles renumbered
+// from 0 make the layout of that sort.
 static int sort_new_if_flagged(Batch *b, int nx, hipStream_t st) {
     if (!b->mk_ok) return PR_OK;
     PR_HIP(hipMemcpyAsync(b->flag_host, b->flag, sizeof(int), hipMemcpyDeviceToHost, st));
     PR_HIP(hipStreamSynchronize(st));
     if (*b->flag_host == 0) return PR_OK;
-    SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
-    PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, b->Q, b->qR, nullptr, b->ws, st));
+    const int nseg = (int)b->seg_f_h.size();
+    PR_HIP(hipMemcpyAsync(b->segflag_host, b->segflag, sizeof(int) * nseg, hipMemcpyDeviceToHost, st));
+    PR_HIP(hipStreamSynchronize(st));
+    int nsub = 0;
+    int64_t tiles = 0, max_n = 0;
+    for (int s = 0; s < nseg; ++s) {
+        if (!b->segflag_host[s]) continue;
+        SortSeg g = b->seg_f_h[s];
+        g.tile0 = tiles;
+        for (int t = 0; t < g.nblk; ++t) b->tile_sub_h[tiles + t] = nsub;
+        b->seg_sub_h[nsub++] = g;
+        tiles += g.nblk;
+        max_n = std::max(max_n, g.n);
+    }
+    PR_REQUIRE(nsub > 0 && tiles <= b->tiles_f, "matched-knot flags inconsistent");
+    PR_HIP(hipMemcpyAsync(b->seg_sub, b->seg_sub_h, sizeof(SortSeg) * nsub, hipMemcpyHostToDevice, st));
+    PR_HIP(hipMemcpyAsync(b->tile_sub, b->tile_sub_h, sizeof(int) * tiles, hipMemcpyHostToDevice, st));
+    SortLayout L{0, 0, nsub, b->seg_sub, b->tile_sub, nullptr, max_n};
+    PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, tiles, b->Q, b->qR, nullptr, b->ws, st));
     b->knot_sorts += 1;
+    b->knot_sort_segs += nsub;
     return PR_OK;
 }
 
@@ -570,7 +599,8 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
         // cannot isolate every order statistic the device raises the flag and
         // the host sorts the new states after the iteration (sort_new_if_flagged)
         const int mk = matched_knots_segments(b->ws, b->total_x, (int)b->seg_f_h.size(), b->mk_seg, b->mk_gseg,
-                                              b->mk_chunks, b->mk_groups, Q, b->qn, b->qf, b->qR, b->flag, st);
+                                              b->mk_chunks, b->mk_groups, Q, b->qn, b->qf, b->qR, b->flag,
+                                              b->segflag, st);
         if (mk != PR_OK && mk != PR_E_UNSUPPORTED) return mk;
         b->mk_ok = mk == PR_OK;
         if (!b->mk_ok)
@@ -776,6 +806,13 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
         PR_CHECK(upload(b->mk_gseg, gseg, st));
         PB_ALLOC(b->flag, sizeof(int));
         PR_HIP(hipHostMalloc((void **)&b->flag_host, sizeof(int), hipHostMallocDefault));
+        const size_t nseg = b->seg_f_h.size();
+        PB_ALLOC(b->segflag, sizeof(int) * nseg);
+        PR_HIP(hipHostMalloc((void **)&b->segflag_host, sizeof(int) * nseg, hipHostMallocDefault));
+        PB_ALLOC(b->seg_sub, sizeof(SortSeg) * nseg);
+        PR_HIP(hipHostMalloc((void **)&b->seg_sub_h, sizeof(SortSeg) * nseg, hipHostMallocDefault));
+        PB_ALLOC(b->tile_sub, sizeof(int) * (size_t)tiles);
+        PR_HIP(hipHostMalloc((void **)&b->tile_sub_h, sizeof(int) * (size_t)tiles, hipHostMallocDefault));
     }
     // the sort arrays are indexed like the states (segment bases are state offsets)
     int64_t max_inst_keys = 0, max_inst_tiles = 0;
@@ -968,6 +1005,13 @@ extern "C" int pr_parareal_batch_info(const void *hv, int *tuned_block, int *tun
         *particle_steps = w;
     }
     return PR_OK;
+}
+
+extern "C" int pr_parareal_batch_knot_sorts(const void *hv, int64_t *segments) {
+    if (!hv) return -1;
+    const Batch *b = (const Batch *)hv;
+    if (segments) *segments = b->knot_sort_segs;
+    return b->knot_sorts;
 }
 
 extern "C" int pr_parareal_batch_destroy(void *h) {

@@ -228,7 +228,7 @@ struct MkSeg {
 };
 int matched_knots_segments(const void *ws, int64_t total_keys, int nseg, const MkSeg *segs, const int *group_seg,
                            int64_t total_chunks, int64_t total_groups, int nq, const double *qt, const double *qp,
-                           double *q, int *flag, hipStream_t st);
+                           double *q, int *flag, int *segflag, hipStream_t st);
 
 // x_in/y_in and x_out/y_out may alias (in place).
 int fine_propagate(const pr_sde *sde, const pr_schedule *sch, uint64_t seed, uint32_t inst, int64_t n,

@@ -1177,7 +1177,8 @@ struct MkArgs {
     const int *group_seg;
     void *pre, *suf, *gx, *gn;  // extremes: [chunks], [chunks], [groups], [groups]
     int nq;
-    int *flag;
+    int *flag;     // raised where some ensemble's knots need the sort
+    int *segflag;  // unequal lengths: one flag per ensemble, or NULL
 };
 
 // One ensemble as the kernels see it.
@@ -1392,12 +1393,12 @@ __device__ __forceinline__ uint64_t chunk_cuts(const K *sorted, int64_t n, const
     return __ballot(cut);
 }
 
-// Key of the order statistic of rank r (the wave); sets *flag where the
-// cuts around r are not found within MK_REACH chunks or lie more than 64
-// ranks apart.
+// Key of the order statistic of rank r (the wave); sets *flag (and the
+// ensemble's flag when there is one) where the cuts around r are not found
+// within MK_REACH chunks or lie more than 64 ranks apart.
 template <typename K>
 __device__ K order_stat(const K *sorted, int64_t n, const MkExt<K> &E, int64_t r, const double *dk, double nd,
-                        double Q, int lane, int *flag) {
+                        double Q, int lane, int *flag, int *segflag) {
     const int64_t nch = E.nch;
     const int64_t c = r / 64;
     const int off = (int)(r - c * 64);
@@ -1420,7 +1421,10 @@ __device__ K order_stat(const K *sorted, int64_t n, const MkExt<K> &E, int64_t r
         if (m) b = cc * 64 + __builtin_ctzll(m);
     }
     if (a < 0 || b < 0 || b - a > 64) {
-        if (lane == 0) *flag = 1;
+        if (lane == 0) {
+            *flag = 1;
+            if (segflag) *segflag = 1;
+        }
         return 0;
     }
     // rank r - a among z_a..z_{b-1}: count the smaller keys (ties by position)
@@ -1452,18 +1456,19 @@ __global__ void __launch_bounds__(256) mk_knots(MkArgs A) {
     const MkExt<K> E{(const K *)A.pre + R.ch0, (const K *)A.suf + R.ch0, (const K *)A.gx + R.gr0,
                      (const K *)A.gn + R.gr0, R.nch, R.ngr};
     int *flag = A.flag;
+    int *segflag = (VAR && A.segflag) ? A.segflag + blockIdx.y : nullptr;
     const double nd = (double)n, Q = (double)nq;
     const double t = (double)((int64_t)j * n) / (double)nq - 0.5;
     double v;
     if (t <= 0.0) {
-        v = value_of(order_stat<K>(sorted, n, E, 0, dk, nd, Q, lane, flag));
+        v = value_of(order_stat<K>(sorted, n, E, 0, dk, nd, Q, lane, flag, segflag));
     } else if (t >= (double)(n - 1)) {
-        v = value_of(order_stat<K>(sorted, n, E, n - 1, dk, nd, Q, lane, flag));
+        v = value_of(order_stat<K>(sorted, n, E, n - 1, dk, nd, Q, lane, flag, segflag));
     } else {
         const int64_t r = (int64_t)floor(t);
         const double f = t - (double)r;
-        const double a = value_of(order_stat<K>(sorted, n, E, r, dk, nd, Q, lane, flag));
-        const double b = value_of(order_stat<K>(sorted, n, E, r + 1, dk, nd, Q, lane, flag));
+        const double a = value_of(order_stat<K>(sorted, n, E, r, dk, nd, Q, lane, flag, segflag));
+        const double b = value_of(order_stat<K>(sorted, n, E, r + 1, dk, nd, Q, lane, flag, segflag));
         v = a + f * (b - a);
         v = v < b ? v : b;
     }
@@ -1705,6 +1710,11 @@ static int launch_matched_knots(const MkArgs &A, unsigned ngroups_or_x, int nseg
     const size_t lds = (size_t)(A.nq + 1) * sizeof(double);
     hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)A.flag, (int64_t)1);
     PR_LAUNCHED();
+    if (A.segflag) {
+        hipLaunchKernelGGL(zero_u32, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, (uint32_t *)A.segflag,
+                           (int64_t)nseg);
+        PR_LAUNCHED();
+    }
     const dim3 eg = VAR ? dim3(ngroups_or_x) : dim3(ngroups_or_x, (unsigned)nseg);
     hipLaunchKernelGGL((mk_extremes<K, VAR>), eg, dim3(256), lds, st, A);
     PR_LAUNCHED();
@@ -1736,13 +1746,13 @@ static int matched_knots_impl(const void *ws, int64_t n, int k, int nq, const do
     void *scratch;
     key_buffers<K>(ws, kb, &sorted, &scratch);
     K *pre = (K *)scratch, *suf = pre + nch * k, *gx = suf + nch * k, *gn = gx + ngr * k;
-    const MkArgs A{sorted, n, nch, ngr, qt, qp, qts, qps, q, nullptr, nullptr, pre, suf, gx, gn, nq, flag};
+    const MkArgs A{sorted, n, nch, ngr, qt, qp, qts, qps, q, nullptr, nullptr, pre, suf, gx, gn, nq, flag, nullptr};
     return launch_matched_knots<K, false>(A, (unsigned)ngr, k, st);
 }
 
 int matched_knots_segments(const void *ws, int64_t total_keys, int nseg, const MkSeg *segs, const int *group_seg,
                            int64_t total_chunks, int64_t total_groups, int nq, const double *qt, const double *qp,
-                           double *q, int *flag, hipStream_t st) {
+                           double *q, int *flag, int *segflag, hipStream_t st) {
     const size_t kb = align256((size_t)total_keys * sizeof(uint64_t));
     if ((size_t)2 * (total_chunks + total_groups) * sizeof(uint64_t) > kb) return PR_E_UNSUPPORTED;
     const void *sorted;
@@ -1750,7 +1760,7 @@ int matched_knots_segments(const void *ws, int64_t total_keys, int nseg, const M
     key_buffers<uint64_t>(ws, kb, &sorted, &scratch);
     uint64_t *pre = (uint64_t *)scratch, *suf = pre + total_chunks, *gx = suf + total_chunks,
              *gn = gx + total_groups;
-    const MkArgs A{sorted, 0, 0, 0, qt, qp, 0, 0, q, segs, group_seg, pre, suf, gx, gn, nq, flag};
+    const MkArgs A{sorted, 0, 0, 0, qt, qp, 0, 0, q, segs, group_seg, pre, suf, gx, gn, nq, flag, segflag};
     return launch_matched_knots<uint64_t, true>(A, (unsigned)total_groups, nseg, st);
 }
 

@@ -233,3 +233,58 @@ def test_batched_workload_full_size_first_iteration(torch_dev):
             assert torch.equal(qb, q), i
     finally:
         pr.pr_parareal_batch_destroy(h)
+
+
+def test_batched_workload_flagged_ensembles_sorted_alone(torch_dev):
+    """The full-size batched workload over three iterations (one in batched
+    launches, two graph replays) against the same three iterations instance
+    by instance: the knots of every state of every instance agree bit for
+    bit.  In these iterations the matched-knot kernels cannot isolate some
+    order statistics of a few new states; only the ensembles so flagged are
+    sorted (fewer than all of them), and their knots still agree."""
+    torch = torch_dev
+    _say("batched workload flagged ensembles")
+    draw = torch.empty((256, 4), dtype=torch.float64, device="cuda")
+    pr.pr_draw_instances(0, 256, draw)
+    d = draw.cpu().numpy()
+    sdes, scheds, ns = [], [], []
+    for eps, lam, lg, K in d:
+        dt = eps / 20
+        S = int(round(2.0 / dt))
+        sdes.append(pr.Sde(lam=float(lam), eps=float(eps), beta=2.0))
+        scheds.append(pr.Schedule(S, int(K), 2.0 / S))
+        ns.append(2 ** int(lg))
+    grid = pr.Grid(n_cells=200, n_q=100)
+    rows = sum(sc.n_slices + 1 for sc in scheds)
+    segments = sum(sc.n_slices for sc in scheds)
+
+    def knots(h):
+        out = torch.empty((rows, 101), dtype=torch.float64, device="cuda")
+        r = 0
+        for i, sc in enumerate(scheds):
+            for t in range(sc.n_slices + 1):
+                pr.pr_parareal_batch_state(h, i, t, q=out[r])
+                r += 1
+        torch.cuda.synchronize()
+        return out.cpu()
+
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    with torch.cuda.stream(stream):
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, 0, flags=pr.PR_AUTOTUNE)
+        try:
+            pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED)
+            pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH)
+            sorts, sorted_segs = pr.pr_parareal_batch_knot_sorts(h)
+            qa = knots(h)
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+        _say(f"  knot sorts {sorts}, ensembles sorted {sorted_segs} of {segments} per iteration")
+        h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, 0)
+        try:
+            pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_PER_INSTANCE)
+            qb = knots(h)
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+    assert torch.equal(qa, qb)
+    assert sorts >= 1, "no flagged ensemble in these iterations: the per-ensemble sort was not exercised"
+    assert 0 < sorted_segs < sorts * segments
