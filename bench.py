@@ -45,6 +45,12 @@ WORKLOAD = dict(lam=1.0, beta=2.0, eps=0.01, n=2 ** 20, dt=1e-4, T=10.0, K=64, c
 # isolated builds of each part.  The figure changes only with the method's
 # arithmetic, so that the fraction moves with speed alone.
 VALU_OPS_PER_STEP = 79
+# What the compiled kernel issues per particle-step by SQ_INSTS_VALU (157.06
+# per wave-step of two particles, the loop's own compare included), valid
+# while the sources hash to FINE_SOURCES_SHA256: one fewer than the frozen
+# figure since the slow part's cubic and linear terms are one polynomial in x
+# (update 9).  Its rate against the peak is the issue utilisation.
+KERNEL_VALU_PER_STEP = 157.06 / 2
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = VALU lane-ops/s
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12  # B/s
@@ -54,14 +60,16 @@ FP64_PEAK = 78.6e12
 # eq. (EMx)/(EMy) with dt folded into the coefficients: slow part 11
 # (d = x - y, x^2, (-dt c3) x^2 and four fused multiply-adds of two flops:
 # the cubic, linear and coupling terms and the noise), fast part 4 (two fused
-# multiply-adds, d shared).  The normals' own arithmetic is not counted.
+# multiply-adds, d shared).  The normals' own arithmetic is not counted.  The
+# kernel now takes the cubic and linear terms as one polynomial in x (14
+# flops); the figure stays, like VALU_OPS_PER_STEP.
 FP64_FLOP_PER_STEP = 15
 
 # HBM bytes of one launch of the fine kernel (all 64 slices) from two
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
 # + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
-FINE_TRAFFIC_BYTES = (524410 * 2 + 1048576) * 1024
-FINE_SOURCES_SHA256 = "fc0b10586a5cda115f1bc7973b4b0b703f7a1c30fb04dd2ce34511e9e92ba987"
+FINE_TRAFFIC_BYTES = (524412 * 2 + 1048576) * 1024
+FINE_SOURCES_SHA256 = "4ab189c6707f32bed408450f6c57506ee8c3eac019b49344ceb9d54a9df6fb90"
 FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
                 "pr_noise_tables.inc"]
 
@@ -615,7 +623,9 @@ def main():
                     traffic_algorithmic=n * K * 32,
                     kernel="fine_kernel<1,double,2> (all 64 slices, one launch)",
                     fine_ms=phases["fine"], fine_particle_steps_per_s=fine_rate,
-                    ops_per_particle_step=VALU_OPS_PER_STEP)
+                    ops_per_particle_step=VALU_OPS_PER_STEP,
+                    kernel_ops_per_particle_step=KERNEL_VALU_PER_STEP if traffic is not None else None,
+                    issue_frac=KERNEL_VALU_PER_STEP * fine_rate / VALU_PEAK if traffic is not None else None)
 
     # the whole iteration against its floor: the fine steps at the VALU issue
     # peak plus the algorithmic bytes of restriction (8 B key read + 4 B rank
@@ -691,7 +701,9 @@ def summary_line(d, args, config):
                             quantile_levels=config["quantile_levels"], flags=config["flags"]))
     line["roofline"] = dict(bound=r["bound"], achieved=_sig(r["achieved"]), peak=_sig(r["peak"]), unit=r["unit"],
                             frac=_sig(r["frac"]), traffic=r["traffic"], kernel=r["kernel"],
-                            ops_per_particle_step=r["ops_per_particle_step"], fine_ms=_sig(r["fine_ms"]),
+                            ops_per_particle_step=r["ops_per_particle_step"],
+                            kernel_ops_per_particle_step=_sig(r.get("kernel_ops_per_particle_step")),
+                            issue_frac=_sig(r.get("issue_frac")), fine_ms=_sig(r["fine_ms"]),
                             fp64_flop_per_particle_step=FP64_FLOP_PER_STEP,
                             fp64_tflops=_sig(FP64_FLOP_PER_STEP * r["fine_particle_steps_per_s"] / 1e12),
                             fp64_flop_frac=_sig(FP64_FLOP_PER_STEP * r["fine_particle_steps_per_s"] / FP64_PEAK))

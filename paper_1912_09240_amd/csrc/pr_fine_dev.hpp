@@ -57,12 +57,12 @@ __device__ __forceinline__ void em_step(T &x, T (&y)[D], const T (&a)[D], const 
     }
     // fused multiply-adds written out, everything else unfused, so that every
     // kernel that inlines this step produces the same bits:
-    //   x' = x - dt lam (x - ybar) - dt c1 x - dt c3 x^3 + sx z0
+    //   x' = x - dt lam (x - ybar) - dt (c1 + c3 x^2) x + sx z0
     const T d = x - ybar;
     const T x2 = x * x;
+    const T cx = fmaf_t(c.a3, x2, c.a1);
     T t = fmaf_t(c.al, d, x);
-    t = fmaf_t(c.a1, x, t);
-    t = fmaf_t(c.a3 * x2, x, t);
+    t = fmaf_t(cx, x, t);
     const T xn = fmaf_t(c.sx, z[0], t);
     if constexpr (D == 1) {
         // y' = y + (dt/eps) (x - y) + sy z1
