@@ -71,10 +71,13 @@ __global__ void __launch_bounds__(256) fwd_ckpt_kernel(double *__restrict__ x, d
                 ckpt[(cidx * 2 + 1) * n + pp[q]] = yv[q];
             }
         const int64_t m1 = m0 + every < S ? m0 + every : S;
-        for (int64_t m = m0; m < m1; ++m) {
+        // 32-bit step counter (the generator's counter word is 32 bits wide)
+        const uint32_t mb = (uint32_t)m0, steps = (uint32_t)(m1 - m0);
+#pragma unroll 2
+        for (uint32_t i = 0; i < steps; ++i) {
 #pragma unroll
             for (int q = 0; q < CK_PPT; ++q)
-                em_step_d1(xv[q], yv[q], ec, tab, key, inst, (uint32_t)m, (uint32_t)pp[q]);
+                em_step_d1(xv[q], yv[q], ec, tab, key, inst, mb + i, (uint32_t)pp[q]);
         }
     }
 #pragma unroll

@@ -87,12 +87,15 @@ __global__ void __launch_bounds__(256) fine_batch_kernel(const Unit *__restrict_
     for (;;) {
         if (threadIdx.x == 0) u_sh = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int u = u_sh;
+        // the unit is the block's: in scalar registers, so are its instance's
+        // coefficients and the step range
+        const int u = __builtin_amdgcn_readfirstlane(u_sh);
         __syncthreads();
         if (u >= n_units) break;  // every wave reaches this once the queue is empty
         const Unit U = units[u];
         const InstDev I = insts[U.inst];
-        const int64_t m0 = slice_begin(I.S, I.K, U.slice), m1 = slice_begin(I.S, I.K, U.slice + 1);
+        const int64_t m0 = uniform_i64(slice_begin(I.S, I.K, U.slice));
+        const int64_t m1 = uniform_i64(slice_begin(I.S, I.K, U.slice + 1));
         const int64_t src = I.xoff + (int64_t)U.slice * I.n, dst = src + I.n;
         double xv[PPT], yv[PPT][1];
         bool live[PPT];
@@ -105,9 +108,12 @@ __global__ void __launch_bounds__(256) fine_batch_kernel(const Unit *__restrict_
             xv[q] = xin[src + pp[q]];
             yv[q][0] = yin[src + pp[q]];
         }
-        for (int64_t m = m0; m < m1; ++m) {
+        // 32-bit step counter (the generator's counter word is 32 bits wide)
+        const uint32_t mb = (uint32_t)m0, steps = (uint32_t)(m1 - m0);
+#pragma unroll 2
+        for (uint32_t i = 0; i < steps; ++i) {
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) em_step<1, double>(xv[q], yv[q], a1, I.c, tab, key, I.inst, (uint32_t)m, pp[q]);
+            for (int q = 0; q < PPT; ++q) em_step<1, double>(xv[q], yv[q], a1, I.c, tab, key, I.inst, mb + i, pp[q]);
         }
 #pragma unroll
         for (int q = 0; q < PPT; ++q)

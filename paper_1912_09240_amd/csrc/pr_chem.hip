@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(256) chem_fine_kernel(const double *xin, const
     load_noise_tab(tab);
     const int s = blockIdx.y;
     const int sl = slice_first + s;
-    const int64_t m0 = slice_begin(S, N, sl);
-    const int64_t m1 = slice_begin(S, N, sl + 1);
+    const int64_t m0 = uniform_i64(slice_begin(S, N, sl));
+    const int64_t m1 = uniform_i64(slice_begin(S, N, sl + 1));
     const int64_t base = (int64_t)blockIdx.x * blockDim.x * PPT + threadIdx.x;
     double xv[PPT], yv[PPT];
 #pragma unroll
@@ -85,10 +85,13 @@ __global__ void __launch_bounds__(256) chem_fine_kernel(const double *xin, const
         xv[q] = xin[(int64_t)s * n + pc];
         yv[q] = yin[(int64_t)s * n + pc];
     }
-    for (int64_t m = m0; m < m1; ++m) {
+    // 32-bit step counter (the generator's counter word is 32 bits wide)
+    const uint32_t mb = (uint32_t)m0, steps = (uint32_t)(m1 - m0);
+#pragma unroll 2
+    for (uint32_t i = 0; i < steps; ++i) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
-            chem_step(xv[q], yv[q], c, tab, key, inst, (uint32_t)m, (uint32_t)(base + (int64_t)q * blockDim.x));
+            chem_step(xv[q], yv[q], c, tab, key, inst, mb + i, (uint32_t)(base + (int64_t)q * blockDim.x));
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {

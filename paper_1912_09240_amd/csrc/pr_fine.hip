@@ -21,8 +21,10 @@ __global__ void __launch_bounds__(256, (D >= 32 ? (sizeof(T) == 4 ? 4 : 3) : 1))
     load_noise_tab(tab);
     const int s = blockIdx.y;
     const int sl = slice_first + s;
-    const int64_t m0 = slice_begin(S, N, sl);
-    const int64_t m1 = slice_begin(S, N, sl + 1);
+    // the slice's step range is the block's: keep it in scalar registers so
+    // that the step loop's compare runs on the scalar unit
+    const int64_t m0 = uniform_i64(slice_begin(S, N, sl));
+    const int64_t m1 = uniform_i64(slice_begin(S, N, sl + 1));
     T a[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) a[i] = a_dev ? (T)a_dev[i] : (T)1;
@@ -40,10 +42,13 @@ __global__ void __launch_bounds__(256, (D >= 32 ? (sizeof(T) == 4 ? 4 : 3) : 1))
 #pragma unroll
         for (int i = 0; i < D; ++i) yv[q][i] = yin[((int64_t)s * D + i) * n + pc];
     }
-    for (int64_t m = m0; m < m1; ++m) {
+    // 32-bit step counter (the generator's counter word is 32 bits wide)
+    const uint32_t mb = (uint32_t)m0, steps = (uint32_t)(m1 - m0);
+#pragma unroll 2
+    for (uint32_t i = 0; i < steps; ++i) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
-            em_step<D, T>(xv[q], yv[q], a, c, tab, key, inst, (uint32_t)m, (uint32_t)(base + (int64_t)q * blockDim.x));
+            em_step<D, T>(xv[q], yv[q], a, c, tab, key, inst, mb + i, (uint32_t)(base + (int64_t)q * blockDim.x));
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {

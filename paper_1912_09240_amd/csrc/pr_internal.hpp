@@ -70,6 +70,15 @@ __host__ __device__ inline int64_t slice_begin(int64_t S, int N, int n) {
     return (int64_t)((__int128)n * S / N);
 }
 
+// A value the caller knows to be equal in every lane, moved to scalar
+// registers (the first lane's copy): the slice bounds above come out of a
+// 128-bit division done on the vector unit.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // Noise.  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
 //   (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
