@@ -353,6 +353,14 @@ struct Batch {
     int *tile_f = nullptr;
     int64_t tiles_f = 0, keys_f = 0, seg_max_n = 0;
     std::vector<SortSeg> seg_f_h;
+    // the same ensembles in two layouts for the sort of every iteration:
+    // those the splitter sort takes, and the rest (radix passes)
+    struct Part {
+        SortSeg *seg = nullptr;
+        int *tile = nullptr;
+        int nseg = 0;
+        int64_t tiles = 0, min_n = 0, max_n = 0;
+    } part[2];
     // matching
     MatchSeg *mseg = nullptr;
     int *mtile = nullptr;
@@ -385,7 +393,8 @@ static void batch_free(Batch *b) {
     if (!b) return;
     void *ptrs[] = {b->inst, b->x[0], b->x[1], b->y[0], b->y[1], b->q, b->qn, b->qR, b->qf, b->qcs, b->rank,
                     b->ws, b->E, b->cu, b->chain, b->rho_a, b->units, b->counter, b->seg_f, b->tile_f, b->mseg,
-                    b->mtile, b->mk_seg, b->mk_gseg, b->flag, b->segflag, b->seg_sub, b->tile_sub};
+                    b->mtile, b->mk_seg, b->mk_gseg, b->flag, b->segflag, b->seg_sub, b->tile_sub,
+                    b->part[0].seg, b->part[0].tile, b->part[1].seg, b->part[1].tile};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &gx : b->graph)
@@ -581,7 +590,11 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
     if (mode == 0) {
         PR_CHECK(fine_batch(b, b->n_units, c, nx, st));
         SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
-        PR_CHECK(restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, Q, b->qf, b->rank, b->ws, st));
+        for (const Batch::Part &P : b->part) {
+            if (P.nseg == 0) continue;
+            const SortLayout LP{0, 0, P.nseg, P.seg, P.tile, nullptr, P.max_n, P.min_n};
+            PR_CHECK(restrict_segments(b->x[nx], PR_F64, LP, b->total_x, P.tiles, Q, b->qf, b->rank, b->ws, st));
+        }
         const double *cin = (b->flags & PR_REUSE_COARSE) ? b->q : b->qR;
         hipLaunchKernelGGL(k2m_units, dim3(b->total_slices), dim3(256), sizeof(double) * (g.nq + g.cells + 2), st,
                            cin, (const CoarseUnit *)b->cu, b->rho_a, g);
@@ -798,6 +811,25 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
     b->keys_f = keys;
     PR_CHECK(upload(b->seg_f, b->seg_f_h, st));
     PR_CHECK(upload(b->tile_f, tile_seg, st));
+    for (int k = 0; k < 2; ++k) {
+        Batch::Part &P = b->part[k];
+        std::vector<SortSeg> segs;
+        std::vector<int> tl;
+        for (const SortSeg &g0 : b->seg_f_h) {
+            if (splitter_sorts(g0.n) != (k == 0)) continue;
+            SortSeg g = g0;
+            g.tile0 = P.tiles;
+            for (int t = 0; t < g.nblk; ++t) tl.push_back((int)segs.size());
+            segs.push_back(g);
+            P.tiles += g.nblk;
+            P.min_n = P.min_n == 0 ? g.n : std::min(P.min_n, g.n);
+            P.max_n = std::max(P.max_n, g.n);
+        }
+        P.nseg = (int)segs.size();
+        if (P.nseg == 0) continue;
+        PR_CHECK(upload(P.seg, segs, st));
+        PR_CHECK(upload(P.tile, tl, st));
+    }
     {
         std::vector<MkSeg> mk;
         std::vector<int> gseg;

@@ -263,8 +263,12 @@ struct SortLayout {
     const int *tile_seg;   // unequal lengths: device table [tiles]
     const int *guard;      // device flag or NULL: while it reads 0 every kernel of the sort returns at once
     int64_t max_n;         // unequal lengths: the longest segment (0 if not known)
+    int64_t min_n;         // unequal lengths: the shortest segment (0 if not known)
 };
 int64_t sort_tiles(int64_t n);
+// Whether an FP64 ensemble of n keys is sorted by splitters and buckets
+// (with ranks or the permutation asked for) rather than by radix passes.
+bool splitter_sorts(int64_t n);
 size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int precision, bool payload);
 int restrict_segments(const void *x, int precision, const SortLayout &L, int64_t total_keys, int64_t total_tiles,
                       int nq, double *q, uint32_t *rank, void *ws, hipStream_t st);

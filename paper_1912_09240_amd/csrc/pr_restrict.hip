@@ -454,7 +454,14 @@ constexpr int SS_CAP = SS_BT * SS_IT;       // 7168: two bucket blocks share a C
 constexpr int SS_SUB = 2048;
 constexpr int SS_SUBMAX = 512;
 constexpr int64_t SS_MIN_N = (int64_t)1 << 16;
+constexpr int64_t SS_MAX_N = (int64_t)3 << 19;  // 1.5 M keys: SS_B buckets of 6144 on average
 static_assert(SS_B == RS_RADIX, "buckets take the place of a radix pass's digits");
+
+// Buckets of an ensemble of n keys: about 4096 keys each, between 1 and SS_B.
+__host__ __device__ __forceinline__ int ss_buckets(int64_t n) {
+    const int64_t b = n >> 12;
+    return b < 1 ? 1 : (b > SS_B ? SS_B : (int)b);
+}
 static_assert(SS_SUB == 2 * SS_BT, "two sub-bucket counts per thread");
 
 // Bucket of a key: the number of splitters sp[1..SS_B-1] at or below it.
@@ -466,12 +473,16 @@ __device__ __forceinline__ uint32_t ss_bucket_of(uint64_t key, const uint64_t *s
     return b;
 }
 
+template <bool VAR>
 __global__ void __launch_bounds__(SS_RUN / 2) ss_sample_runs(const double *__restrict__ x, SortLayout L,
                                                             uint64_t *__restrict__ runq) {
     __shared__ uint64_t sk[SS_RUN];
     const int r = blockIdx.x, s = blockIdx.y, t = threadIdx.x;
-    const int64_t n = L.n, total = (int64_t)SS_RUNS * SS_RUN;
-    const double *xs = x + (int64_t)s * n;
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, s, base, n, tile0, nblk, qrow);
+    const int64_t total = (int64_t)SS_RUNS * SS_RUN;
+    const double *xs = x + base;
     for (int i = t; i < SS_RUN; i += blockDim.x) {
         const int64_t g = (int64_t)r * SS_RUN + i;
         sk[i] = key_of(xs[g * n / total]);
@@ -492,18 +503,31 @@ __global__ void __launch_bounds__(SS_RUN / 2) ss_sample_runs(const double *__res
         runq[((int64_t)s * SS_RUNS + r) * SS_B + b] = sk[b * (SS_RUN / SS_B)];
 }
 
-// Splitter b: the mean over the runs of their b-th quantile value, each
-// value first clamped to the finite range (infinities and NaN to the end of
-// the range their key sorts to).  The clamped value is non-decreasing in the
+// Splitter b of an ensemble with B buckets: the mean over the runs of their
+// quantile value at level b/B (the run's quantile b SS_B / B), each value
+// first clamped to the finite range (infinities and NaN to the end of the
+// range their key sorts to).  The clamped value is non-decreasing in the
 // key, so the means are non-decreasing in b; averaging in the value domain
 // keeps the splitters where the values lie (the key domain is far from
-// linear in the value around 0).
-__global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict__ runq, uint64_t *__restrict__ split) {
+// linear in the value around 0).  Splitters B..SS_B-1 are the largest key:
+// buckets past B stay empty (a key equal to it goes to bucket B - 1).
+template <bool VAR>
+__global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict__ runq, SortLayout L,
+                                                     uint64_t *__restrict__ split) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x, b = threadIdx.x;
+    int64_t base, n, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, s, base, n, tile0, nblk, qrow);
+    const int nb = ss_buckets(n);
+    if (b >= nb) {
+        split[(int64_t)s * SS_B + b] = ~0ull;
+        return;
+    }
+    const int j = (int)(((int64_t)b * SS_B) / nb);
     double acc = 0.0;
     for (int r = 0; r < SS_RUNS; ++r) {
-        const uint64_t k = runq[((int64_t)s * SS_RUNS + r) * SS_B + b];
+        const uint64_t k = runq[((int64_t)s * SS_RUNS + r) * SS_B + j];
         double v = value_of(k);
         if (v != v) v = (k >> 63) ? 1.79e308 : -1.79e308;
         v = fmin(fmax(v, -1.79e308), 1.79e308);
@@ -518,6 +542,7 @@ __global__ void __launch_bounds__(SS_B) ss_splitters(const uint64_t *__restrict_
 constexpr int SC_THREADS = 2 * RS_THREADS;
 constexpr int SC_WAVES = SC_THREADS / 64;
 
+template <bool VAR>
 __global__ void __launch_bounds__(SC_THREADS)
 ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, SortLayout L,
          uint32_t *__restrict__ counts, double *__restrict__ mom_part, HistArgs ha, uint8_t *__restrict__ bucket) {
@@ -526,7 +551,7 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
     __shared__ double wsum[SC_WAVES][4];
     __shared__ uint64_t sp[SS_B];
     extern __shared__ uint32_t cell_h[];
-    const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < SC_WAVES * 2 * RS_RADIX; i += SC_THREADS) (&h[0][0][0])[i] = 0;
     for (int i = tid; i < SS_B; i += SC_THREADS) sp[i] = split[(int64_t)T.seg * SS_B + i];
@@ -544,8 +569,12 @@ ss_count(const double *__restrict__ src, const uint64_t *__restrict__ split, Sor
     // every key's bucket first (loads of LDS only, so the searches of the
     // tile's keys overlap), then the counting
     uint32_t bk[ITEMS];
+    const uint32_t last = (uint32_t)ss_buckets(T.n) - 1;  // the largest key joins the last bucket
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) bk[i] = ss_bucket_of(key_of(in[i]), sp);
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t b = ss_bucket_of(key_of(in[i]), sp);
+        bk[i] = b < last ? b : last;
+    }
     // every key's bucket for the scatter, one byte each
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -623,6 +652,7 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *wtot) 
 // Scatter of (key, particle) into the buckets.  The order inside a bucket
 // is left to the block's LDS atomics: the bucket sort orders by (key,
 // particle) whatever order its input has.
+template <bool VAR>
 __global__ void __launch_bounds__(SC_THREADS)
 ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, uint64_t *__restrict__ keys_out,
            uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ counts,
@@ -635,7 +665,7 @@ ss_scatter(const double *__restrict__ src, const uint8_t *__restrict__ bucket, u
     __shared__ uint64_t stage[TILE];
     __shared__ uint8_t sdig[TILE];
 
-    const TileRef T = tile_ref<false>(L, xcd_tile(blockIdx.x, gridDim.x));
+    const TileRef T = tile_ref<VAR>(L, xcd_tile(blockIdx.x, gridDim.x));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t t0 = (int64_t)T.blk * TILE + wave * WAVE_KEYS;
     if (tid < RS_RADIX) bcnt[tid] = 0;
@@ -716,6 +746,7 @@ __device__ __forceinline__ V ss_block_reduce(V v, V *red, Op op) {
     return r;
 }
 
+template <bool VAR>
 __global__ void __launch_bounds__(SS_BT)
 ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ bvals,
                const uint32_t *__restrict__ totals, const uint32_t *__restrict__ bstart,
@@ -736,8 +767,11 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         if (tid == 0) *flag = 1;
         return;
     }
+    int64_t sbase, sn, tile0;
+    int nblk, qrow;
+    seg_ref<VAR>(L, s, sbase, sn, tile0, nblk, qrow);
     const uint32_t start = bstart[(int64_t)s * SS_B + b];
-    const int64_t base = (int64_t)s * L.n + start;
+    const int64_t base = sbase + start;
     for (int i = tid; i < SS_SUB / 2; i += SS_BT) cursor[i] = 0;
     if (tid == 0) too_big = 0;
     // keys and their particles, both read in order
@@ -752,7 +786,7 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
     // bounds of the bucket's values: its splitters inside, its extremes at
     // the two ends of the ensemble
     uint64_t kmin, kmax;
-    if (b > 0 && b < SS_B - 1) {
+    if (b > 0 && b < ss_buckets(sn) - 1) {
         kmin = split[(int64_t)s * SS_B + b];
         kmax = split[(int64_t)s * SS_B + b + 1];
     } else {
@@ -889,7 +923,7 @@ ss_bucket_sort(const uint64_t *__restrict__ bkeys, const uint32_t *__restrict__ 
         if (idx < size) {
             const uint32_t op = sv[idx];
             if (perm_out) perm_out[base + idx] = op;
-            if (rank_out) rank_out[(int64_t)s * L.n + op] = start + idx;
+            if (rank_out) rank_out[sbase + op] = start + idx;
         }
     }
 }
@@ -1494,6 +1528,8 @@ size_t sort_ws_bytes(int64_t total_keys, int64_t total_tiles, int nseg, int prec
     return b;
 }
 
+bool splitter_sorts(int64_t n) { return n >= SS_MIN_N && n <= SS_MAX_N; }
+
 size_t restrict_ws(int64_t n, int k, int precision) {
     return sort_ws_bytes((int64_t)n * k, sort_tiles(n) * k, k, precision, true);
 }
@@ -1589,33 +1625,44 @@ static int sort_impl(const void *x, const SortLayout &L, int64_t total_keys, int
         return PR_OK;
     };
     constexpr int P = KeyTraits<K>::passes;
+    // The splitter sort takes FP64 ensembles of SS_MIN_N..SS_MAX_N keys (a
+    // segment table says its shortest and longest).
     bool splitter = false;
-    if constexpr (std::is_same<K, uint64_t>::value && !VAR)
-        splitter = payload && L.guard == nullptr && L.n >= SS_MIN_N;
+    if constexpr (std::is_same<K, uint64_t>::value)
+        splitter = payload && L.guard == nullptr &&
+                   (VAR ? (L.min_n >= SS_MIN_N && L.max_n <= SS_MAX_N) : (L.n >= SS_MIN_N && L.n <= SS_MAX_N));
     if (splitter) {
-        if constexpr (std::is_same<K, uint64_t>::value && !VAR) {
+        if constexpr (std::is_same<K, uint64_t>::value) {
             // the splitter sort, then the complete radix sort guarded by its flag
             hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, (uint32_t *)flag, (int64_t)1);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(ss_sample_runs, dim3(SS_RUNS, (unsigned)L.nseg), dim3(SS_RUN / 2), 0, st,
+            hipLaunchKernelGGL((ss_sample_runs<VAR>), dim3(SS_RUNS, (unsigned)L.nseg), dim3(SS_RUN / 2), 0, st,
                                (const double *)x, L, runq);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(ss_splitters, dim3((unsigned)L.nseg), dim3(SS_B), 0, st, (const uint64_t *)runq, split);
+            hipLaunchKernelGGL((ss_splitters<VAR>), dim3((unsigned)L.nseg), dim3(SS_B), 0, st,
+                               (const uint64_t *)runq, L, split);
             PR_LAUNCHED();
             // the bucket of every key, one byte each, in the first payload
             // buffer (free until the bucket sort writes the permutation)
             uint8_t *bucket = (uint8_t *)vals[0];
-            hipLaunchKernelGGL(ss_count, grid, dim3(SC_THREADS), cell_lds, st, (const double *)x,
+            hipLaunchKernelGGL((ss_count<VAR>), grid, dim3(SC_THREADS), cell_lds, st, (const double *)x,
                                (const uint64_t *)split, L, counts, mom ? mom_part : nullptr, ha, bucket);
             PR_LAUNCHED();
-            hipLaunchKernelGGL((rs_rowscan<false>), rows, dim3(256), 0, st, counts, totals, L);
+            if constexpr (VAR)
+                hipLaunchKernelGGL((rs_rowscan_seg<true>), dim3((unsigned)L.nseg), dim3(RS_RADIX), 0, st, counts,
+                                   totals, L);
+            else
+                hipLaunchKernelGGL((rs_rowscan<false>), rows, dim3(256), 0, st, counts, totals, L);
             PR_LAUNCHED();
-            hipLaunchKernelGGL(ss_scatter, grid, dim3(SC_THREADS), 0, st, (const double *)x, (const uint8_t *)bucket,
-                               (uint64_t *)keys[1], vals[1], (const uint32_t *)counts, (const uint32_t *)totals, L,
-                               bstart);
+            hipLaunchKernelGGL((ss_scatter<VAR>), grid, dim3(SC_THREADS), 0, st, (const double *)x,
+                               (const uint8_t *)bucket, (uint64_t *)keys[1], vals[1], (const uint32_t *)counts,
+                               (const uint32_t *)totals, L, bstart);
             PR_LAUNCHED();
             uint32_t *perm_fix = perm ? perm : (staged_ranks ? vals[0] : nullptr);
-            hipLaunchKernelGGL(ss_bucket_sort, dim3((unsigned)SS_B, (unsigned)L.nseg), dim3(SS_BT), 0, st,
+            // one block per bucket of the ensemble with the most (the blocks
+            // of the others' empty buckets return at once)
+            const int nb = ss_buckets(VAR ? L.max_n : L.n);
+            hipLaunchKernelGGL((ss_bucket_sort<VAR>), dim3((unsigned)nb, (unsigned)L.nseg), dim3(SS_BT), 0, st,
                                (const uint64_t *)keys[1], (const uint32_t *)vals[1], (const uint32_t *)totals,
                                (const uint32_t *)bstart, (const uint64_t *)split, L, (uint64_t *)keys[0], perm_fix,
                                staged_ranks ? nullptr : rank, xs, flag);

@@ -102,6 +102,35 @@ def test_launch_modes_bitwise(torch_dev):
     assert np.array_equal(results[4][1][0][0], ref[0][0])
 
 
+# ensembles the splitter sort takes (2^16 keys and more, one of them ragged)
+# beside ones the radix passes sort, in one batch
+LARGE_INSTANCES = [(0.05, 1.3, 65536, 3, 0.1), (0.1, 0.7, 3000, 4, 0.2), (0.02, 1.9, 70001, 2, 0.02),
+                   (0.08, 1.0, 131072, 3, 0.12), (0.03, 0.55, 4096, 5, 0.06)]
+
+
+def test_launch_modes_bitwise_with_large_ensembles(torch_dev):
+    """A batch whose fine results are sorted in two layouts, the ensembles of
+    2^16 keys and more by splitters and buckets (as many buckets as 4096
+    keys fill) and the rest by radix passes: batched launches and graph
+    replays give the bits of instance-by-instance launches (whose sorts take
+    each instance's ensembles alone) over three iterations, states and
+    knots."""
+    torch = torch_dev
+    _say("batch modes, large ensembles")
+    results = []
+    for mode in (pr.PR_LAUNCH_PER_INSTANCE, pr.PR_LAUNCH_BATCHED, pr.PR_LAUNCH_GRAPH):
+        h = _make(torch, 0, inst=LARGE_INSTANCES)
+        try:
+            pr.pr_parareal_batch_iterate(h, 3, mode)
+            results.append(_states(torch, h, inst=LARGE_INSTANCES))
+        finally:
+            pr.pr_parareal_batch_destroy(h)
+    ref = results[0]
+    for st in results[1:]:
+        for (a, b, c), (a0, b0, c0) in zip(st, ref):
+            assert np.array_equal(a, a0) and np.array_equal(b, b0) and np.array_equal(c, c0)
+
+
 def test_batch_matches_oracle_per_instance(torch_dev):
     torch = torch_dev
     _say("batch vs oracle")
