@@ -92,7 +92,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192, help="particles in the oracle's sample")
     ap.add_argument("--flags", type=int, default=0, help="parareal flags (1 reuse coarse, 2 skip converged)")
-    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default="bench_detail.json",
                     help="file for the full measurements (empty: none)")
     return ap.parse_args()
 

@@ -12,7 +12,7 @@ import bench  # noqa: E402
 
 
 class _Args:
-    steps, warmup, detail = 20, 5, "gpurun_out/bench_detail.json"
+    steps, warmup, detail = 20, 5, "bench_detail.json"
 
 
 def _detail():
