@@ -454,7 +454,9 @@ constexpr int SS_CAP = SS_BT * SS_IT;       // 7168: two bucket blocks share a C
 constexpr int SS_SUB = 2048;
 constexpr int SS_SUBMAX = 512;
 constexpr int64_t SS_MIN_N = (int64_t)1 << 16;
-constexpr int64_t SS_MAX_N = (int64_t)3 << 19;  // 1.5 M keys: SS_B buckets of 6144 on average
+// Above this the SS_B buckets average more than 4352 keys, and the largest of
+// them (about 1.5 times the mean with 64 samples per bucket) nears SS_CAP.
+constexpr int64_t SS_MAX_N = ((int64_t)1 << 20) + ((int64_t)1 << 16);
 static_assert(SS_B == RS_RADIX, "buckets take the place of a radix pass's digits");
 
 // Buckets of an ensemble of n keys: about 4096 keys each, between 1 and SS_B.

@@ -304,13 +304,15 @@ def test_restrict_many_small_segments(torch_dev, k, n):
 @pytest.mark.parametrize("k,n,ties,prec", [(1, 1, False, pr.PR_F64), (3, 4097, False, pr.PR_F64),
                                            (4, 70_001, True, pr.PR_F64), (2, 2 ** 20, False, pr.PR_F64),
                                            (2, 2 ** 20, True, pr.PR_F64), (1, 2 ** 20 + 1, False, pr.PR_F64),
+                                           (1, 2 ** 20 + 2 ** 17, False, pr.PR_F64),
                                            (3, 4097, True, pr.PR_F32), (2, 2 ** 20, False, pr.PR_F32),
                                            (1, 2 ** 20 + 1, True, pr.PR_F32)])
 def test_restrict_rank_only(torch_dev, k, n, ties, prec):
     """Ranks asked for alone, as the parareal drivers do: up to 2^20 keys per
     segment they go through the staging buffer, beyond by direct stores; for
     FP64 keys the runs of hundreds of signed zeros of ties=True hand the
-    ranks to the complete sort."""
+    ranks to the complete sort, and ensembles above 2^20 + 2^16 keys are
+    sorted by the radix passes from the start."""
     torch = torch_dev
     _say(f"restrict rank only k={k} n={n} ties={ties} precision={prec}")
     xs = inputs.slow_values(300 + n % 1000, k, n, ties=ties)
