@@ -1,11 +1,14 @@
 // Restriction to the empirical quantile function (Sec. 3.2.2, Sec. 4.4):
-// a segmented, stable LSD radix sort of the slow coordinates of many
-// ensembles (one segment per ensemble, equal or unequal lengths), followed by
+// a segmented sort of the slow coordinates of many ensembles (one segment
+// per ensemble, equal or unequal lengths) by (key, particle), followed by
 // the midpoint (Hazen) knots; the moments (eq. (MCestimator)) and the cell
 // histogram (eq. (binning)) are fused into the first read of the values.
+// FP64 ensembles of SS_MIN_N..SS_MAX_N keys with ranks or the permutation
+// asked for take the splitter sort (sample, buckets, one LDS sort per
+// bucket; described with its kernels below); the rest take the radix sort.
 //
-// Sort design (HBM bound): 8-bit digits, one pass per byte of the orderable
-// key.  A pass is
+// Radix sort design (HBM bound): 8-bit digits, one pass per byte of the
+// orderable key.  A pass is
 //   count   digit histogram of every tile (ITEMS x 256 keys),
 //   rowscan one wave per (segment, digit) -- one block per segment in the
 //           segment-table layout: exclusive prefix of that digit's tile
@@ -420,19 +423,20 @@ rs_scatter(const void *__restrict__ src, const uint32_t *__restrict__ vals_in, K
 }
 
 // ---------------------------------------------------------------------------
-// Splitter sort of large FP64 ensembles (equal lengths, n >= SS_MIN_N): the
-// keys are first distributed over SS_B buckets by splitters drawn from a
-// sample, then every bucket is ordered on its own in LDS.
+// Splitter sort of large FP64 ensembles (SS_MIN_N <= n <= SS_MAX_N; equal
+// lengths or a segment table): the keys of every ensemble are first
+// distributed over ss_buckets(n) buckets (about 4096 keys each) by splitters
+// drawn from a sample, then every bucket is ordered on its own in LDS.
 //   ss_sample_runs  SS_RUNS blocks per ensemble, each sorting SS_RUN keys of
 //                   the sample (positions i n / (SS_RUNS SS_RUN)) in LDS and
 //                   keeping its SS_B quantile keys;
-//   ss_splitters    splitter b = the mean over the runs of their b-th
-//                   quantile value (non-decreasing in b, as every run's
-//                   quantiles are);
+//   ss_splitters    splitter b = the mean over the runs of their quantile
+//                   value at level b / ss_buckets(n) (non-decreasing in b,
+//                   as every run's quantiles are);
 //   ss_count        bucket histogram of every tile and the bucket of every
 //                   key (one byte; the moments and the cell histogram fused
 //                   into this first read of the values);
-//   rs_rowscan      tile offsets and bucket totals, as for a radix pass;
+//   rs_rowscan(_seg) tile offsets and bucket totals, as for a radix pass;
 //   ss_scatter      scatter of (key, particle) into the buckets (in any
 //                   order inside a bucket: slots from LDS atomics);
 //   ss_bucket_sort  one block per bucket: the keys go to value sub-buckets
