@@ -115,7 +115,6 @@ __global__ void __launch_bounds__(256) fine_batch_kernel(const Unit *__restrict_
 #pragma unroll
             for (int q = 0; q < PPT; ++q) em_step<1, double>(xv[q], yv[q], a1, I.c, tab, key, I.inst, mb + i, pp[q]);
         }
-#pragma unroll
         for (int q = 0; q < PPT; ++q)
             if (live[q]) {
                 xout[dst + pp[q]] = xv[q];
