@@ -299,6 +299,7 @@ def batched_measure(torch, pr):
                          "P in 2^12..2^18, N in 8..64 slices, dt = eps/20, T = 2, 200 cells, 100 levels",
                 fine_particle_steps_per_iteration=w, work_units=info["units"],
                 tuned_block=info["block"], tuned_particles_per_thread=info["ppt"],
+                tuned_split_sort=info["split_sort"],
                 sweep_ms_graph=ms_graph, sweep_ms_batched=ms_batched, sweep_ms_per_instance=ms_plain,
                 particle_steps_per_s_graph=w / (ms_graph / 1e3),
                 particle_steps_per_s_per_instance=w / (ms_plain / 1e3),

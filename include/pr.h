@@ -310,8 +310,14 @@ int pr_parareal_destroy(void *h);
  * (instance, slice, particle tile) units from a queue in decreasing cost.
  * pr_parareal_batch_state copies the state of instance inst at time t.
  * pr_parareal_batch_info reports the tuned block size and particles per
- * thread, the number of fine work units and the fine particle-steps of one
- * iteration.  pr_parareal_batch_knot_sorts returns the number of batched
+ * thread, the number of fine work units, the fine particle-steps of one
+ * iteration and how the fine results are sorted (1: ensembles of 2^16 to
+ * 2^20 + 2^16 FP64 keys by splitters and buckets, the rest by radix passes;
+ * 0: all by radix passes).  With PR_AUTOTUNE, creation times the fine
+ * kernel's shapes (block {128, 256} x particles per thread {1, 2, 4}, kept
+ * per device) and the two sorts on the batch's own states (kept per batch;
+ * both give the same bits); without it the defaults are 256, 2 and 1.
+ * Every output pointer (host) may be NULL.  pr_parareal_batch_knot_sorts returns the number of batched
  * iterations whose new knots needed a sort of some new states (where the
  * knots from the fine results' order could not isolate an order statistic),
  * or -1 for h NULL; segments (host, may be NULL) receives how many
@@ -330,7 +336,7 @@ int pr_parareal_batch_create(int n_inst, const pr_sde *sde, const pr_schedule *s
 int pr_parareal_batch_iterate(void *h, int n_iter, int mode, double *ms_out, void *stream);
 int pr_parareal_batch_state(void *h, int inst, int t, void *x, void *y, double *q, void *stream);
 int pr_parareal_batch_info(const void *h, int *tuned_block, int *tuned_ppt, int64_t *units,
-                           int64_t *particle_steps);
+                           int64_t *particle_steps, int *split_sort);
 int pr_parareal_batch_knot_sorts(const void *h, int64_t *segments);
 int pr_parareal_batch_destroy(void *h);
 

@@ -167,7 +167,7 @@ _SIGS = {
     "pr_parareal_batch_iterate": (_c_int, [_vp, _c_int, _c_int, ctypes.POINTER(_c_dbl), _vp]),
     "pr_parareal_batch_state": (_c_int, [_vp, _c_int, _c_int, _vp, _vp, _vp, _vp]),
     "pr_parareal_batch_info": (_c_int, [_vp, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_i64),
-                                        ctypes.POINTER(_c_i64)]),
+                                        ctypes.POINTER(_c_i64), ctypes.POINTER(_c_int)]),
     "pr_parareal_batch_knot_sorts": (_c_int, [_vp, ctypes.POINTER(_c_i64)]),
     "pr_parareal_batch_destroy": (_c_int, [_vp]),
     "pr_fine_adjoint": (_c_int, [ctypes.POINTER(_CSde), ctypes.POINTER(_CSchedule), _c_u64, _c_u32, _c_i64, _vp,
@@ -428,9 +428,10 @@ def pr_parareal_batch_state(h, inst, t, x=None, y=None, q=None, stream=None):
 
 
 def pr_parareal_batch_info(h):
-    b, p, u, w = _c_int(), _c_int(), _c_i64(), _c_i64()
-    _check(lib().pr_parareal_batch_info(h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(u), ctypes.byref(w)))
-    return dict(block=b.value, ppt=p.value, units=u.value, particle_steps=w.value)
+    b, p, u, w, sp = _c_int(), _c_int(), _c_i64(), _c_i64(), _c_int()
+    _check(lib().pr_parareal_batch_info(h, ctypes.byref(b), ctypes.byref(p), ctypes.byref(u), ctypes.byref(w),
+                                        ctypes.byref(sp)))
+    return dict(block=b.value, ppt=p.value, units=u.value, particle_steps=w.value, split_sort=bool(sp.value))
 
 
 def pr_parareal_batch_knot_sorts(h):

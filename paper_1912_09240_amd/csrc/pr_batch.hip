@@ -360,6 +360,7 @@ struct Batch {
         int nseg = 0;
         int64_t tiles = 0, min_n = 0, max_n = 0;
     } part[2];
+    bool split_sort = true;  // the two layouts above (else one radix sort of all ensembles)
     // matching
     MatchSeg *mseg = nullptr;
     int *mtile = nullptr;
@@ -546,6 +547,58 @@ static int autotune(Batch *b, hipStream_t st) {
     return PR_OK;
 }
 
+// Restriction of the fine results (buffer nx): knots into qf, ranks; in the
+// two layouts (splitter sort for the ensembles it takes, radix passes for the
+// rest) or as one segment table by radix passes, as tuned.
+static int restrict_fine(Batch *b, int nx, hipStream_t st) {
+    if (!b->split_sort) {
+        const SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
+        return restrict_segments(b->x[nx], PR_F64, L, b->total_x, b->tiles_f, b->Q, b->qf, b->rank, b->ws, st);
+    }
+    for (const Batch::Part &P : b->part) {
+        if (P.nseg == 0) continue;
+        const SortLayout LP{0, 0, P.nseg, P.seg, P.tile, nullptr, P.max_n, P.min_n};
+        PR_CHECK(restrict_segments(b->x[nx], PR_F64, LP, b->total_x, P.tiles, b->Q, b->qf, b->rank, b->ws, st));
+    }
+    return PR_OK;
+}
+
+// Times the two restrictions of the fine results on the batch's own states
+// (those of the zeroth iteration, the same shapes) and keeps the faster; both
+// give the same bits.  The outputs it writes are rewritten by the first
+// iteration.
+static int tune_sort(Batch *b, hipStream_t st) {
+    if (b->part[0].nseg == 0) {  // no ensemble the splitter sort takes
+        b->split_sort = false;
+        return PR_OK;
+    }
+    hipEvent_t e0, e1;
+    PR_HIP(hipEventCreate(&e0));
+    PR_HIP(hipEventCreate(&e1));
+    double ms_of[2] = {0.0, 0.0};
+    int rc = PR_OK;
+    for (int split = 0; split < 2 && rc == PR_OK; ++split) {
+        b->split_sort = split == 1;
+        rc = restrict_fine(b, b->cur, st);  // warm-up
+        if (rc != PR_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = PR_E_HIP;
+        if (rc == PR_OK) rc = restrict_fine(b, b->cur, st);
+        if (rc == PR_OK && hipEventRecord(e1, st) != hipSuccess) rc = PR_E_HIP;
+        if (rc == PR_OK && hipEventSynchronize(e1) != hipSuccess) rc = PR_E_HIP;
+        float ms = 0.f;
+        if (rc == PR_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PR_E_HIP;
+        ms_of[split] = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PR_OK) {
+        set_error("timing the restriction of the fine results failed");
+        return rc;
+    }
+    b->split_sort = ms_of[1] <= ms_of[0];
+    return PR_OK;
+}
+
 // After a batched iteration (buffer nx holds the new states): where the
 // matched-knot kernels raised the flag, the knots of the new states come from
 // a sort of them.  The host reads the flag once per iteration instead of
@@ -589,11 +642,7 @@ static int iterate_once(Batch *b, int mode, hipStream_t st) {
     if (mode == 0) {
         PR_CHECK(fine_batch(b, b->n_units, c, nx, st));
         SortLayout L{0, 0, (int)b->seg_f_h.size(), b->seg_f, b->tile_f, nullptr, b->seg_max_n};
-        for (const Batch::Part &P : b->part) {
-            if (P.nseg == 0) continue;
-            const SortLayout LP{0, 0, P.nseg, P.seg, P.tile, nullptr, P.max_n, P.min_n};
-            PR_CHECK(restrict_segments(b->x[nx], PR_F64, LP, b->total_x, P.tiles, Q, b->qf, b->rank, b->ws, st));
-        }
+        PR_CHECK(restrict_fine(b, nx, st));
         const double *cin = (b->flags & PR_REUSE_COARSE) ? b->q : b->qR;
         hipLaunchKernelGGL(k2m_units, dim3(b->total_slices), dim3(256), sizeof(double) * (g.nq + g.cells + 2), st,
                            cin, (const CoarseUnit *)b->cu, b->rho_a, g);
@@ -918,7 +967,10 @@ static int batch_create(int B, const pr_sde *sde, const pr_schedule *sch, const 
                        dim3(256), 0, st, (const InstDev *)b->inst, b->x[0], b->y[0], b->x[1], b->y[1]);
     PR_LAUNCHED();
     PR_HIP(hipStreamSynchronize(st));
-    if (flags & PR_AUTOTUNE) PR_CHECK(autotune(b, st));
+    if (flags & PR_AUTOTUNE) {
+        PR_CHECK(autotune(b, st));
+        PR_CHECK(tune_sort(b, st));
+    }
     PR_CHECK(fine_slots(b->tuned, b->persist_blocks));
     build_units(b, b->tuned.block * b->tuned.ppt);
     PR_CHECK(upload(b->units, b->units_h, st));
@@ -1029,12 +1081,13 @@ extern "C" int pr_parareal_batch_state(void *hv, int inst, int t, void *x, void 
 }
 
 extern "C" int pr_parareal_batch_info(const void *hv, int *tuned_block, int *tuned_ppt, int64_t *units,
-                                      int64_t *particle_steps) {
+                                      int64_t *particle_steps, int *split_sort) {
     clear_error();
     PR_REQUIRE(hv != nullptr, "h is NULL");
     const Batch *b = (const Batch *)hv;
     if (tuned_block) *tuned_block = b->tuned.block;
     if (tuned_ppt) *tuned_ppt = b->tuned.ppt;
+    if (split_sort) *split_sort = b->split_sort ? 1 : 0;
     if (units) *units = b->n_units;
     if (particle_steps) {
         int64_t w = 0;

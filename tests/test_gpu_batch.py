@@ -92,6 +92,7 @@ def test_launch_modes_bitwise(torch_dev):
             if flags & pr.PR_AUTOTUNE:
                 info = pr.pr_parareal_batch_info(h)
                 assert info["block"] in (128, 256) and info["ppt"] in (1, 2, 4)
+                assert info["split_sort"] is False  # no ensemble of 2^16 keys here
         finally:
             pr.pr_parareal_batch_destroy(h)
     ref = results[0][1]
@@ -114,13 +115,16 @@ def test_launch_modes_bitwise_with_large_ensembles(torch_dev):
     keys fill) and the rest by radix passes: batched launches and graph
     replays give the bits of instance-by-instance launches (whose sorts take
     each instance's ensembles alone) over three iterations, states and
-    knots."""
+    knots; so do the launches with the fine shape and the sort tuned."""
     torch = torch_dev
     _say("batch modes, large ensembles")
     results = []
-    for mode in (pr.PR_LAUNCH_PER_INSTANCE, pr.PR_LAUNCH_BATCHED, pr.PR_LAUNCH_GRAPH):
-        h = _make(torch, 0, inst=LARGE_INSTANCES)
+    for mode, flags in ((pr.PR_LAUNCH_PER_INSTANCE, 0), (pr.PR_LAUNCH_BATCHED, 0), (pr.PR_LAUNCH_GRAPH, 0),
+                        (pr.PR_LAUNCH_BATCHED, pr.PR_AUTOTUNE)):
+        h = _make(torch, flags, inst=LARGE_INSTANCES)
         try:
+            if flags == 0:
+                assert pr.pr_parareal_batch_info(h)["split_sort"] is True
             pr.pr_parareal_batch_iterate(h, 3, mode)
             results.append(_states(torch, h, inst=LARGE_INSTANCES))
         finally:
@@ -301,13 +305,15 @@ def test_batched_workload_flagged_ensembles_sorted_alone(torch_dev):
     with torch.cuda.stream(stream):
         h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, 0, flags=pr.PR_AUTOTUNE)
         try:
+            info = pr.pr_parareal_batch_info(h)
             pr.pr_parareal_batch_iterate(h, 1, pr.PR_LAUNCH_BATCHED)
             pr.pr_parareal_batch_iterate(h, 2, pr.PR_LAUNCH_GRAPH)
             sorts, sorted_segs = pr.pr_parareal_batch_knot_sorts(h)
             qa = knots(h)
         finally:
             pr.pr_parareal_batch_destroy(h)
-        _say(f"  knot sorts {sorts}, ensembles sorted {sorted_segs} of {segments} per iteration")
+        _say(f"  knot sorts {sorts}, ensembles sorted {sorted_segs} of {segments} per iteration, "
+             f"fine results sorted by splitters: {info['split_sort']}")
         h = pr.pr_parareal_batch_create(sdes, scheds, ns, grid, 0)
         try:
             pr.pr_parareal_batch_iterate(h, 3, pr.PR_LAUNCH_PER_INSTANCE)
