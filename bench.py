@@ -71,7 +71,7 @@ FP64_FLOP_PER_STEP = 15
 # rocprofv3 counter passes, FETCH_SIZE x 2.0 (the factor a 1 GiB copy needs)
 # + WRITE_SIZE, valid while the kernel's sources hash to FINE_SOURCES_SHA256.
 FINE_TRAFFIC_BYTES = (524440 * 2 + 1048576) * 1024
-FINE_SOURCES_SHA256 = "e4a1b0b27e649cf5b0f1383faff43cf2a4a0b783899b603fab3a1700314ff9f2"
+FINE_SOURCES_SHA256 = "ae8a2ccd719189505a28721d0c149e5f8e6851200a8ae949f78d752ad4ff2273"
 FINE_SOURCES = ["pr_fine.hip", "pr_fine_dev.hpp", "pr_internal.hpp", "pr_normal.hpp", "pr_fastmath.hpp",
                 "pr_noise_tables.inc"]
 

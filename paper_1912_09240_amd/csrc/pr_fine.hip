@@ -42,9 +42,11 @@ __global__ void __launch_bounds__(256, (D >= 32 ? (sizeof(T) == 4 ? 4 : 3) : 1))
 #pragma unroll
         for (int i = 0; i < D; ++i) yv[q][i] = yin[((int64_t)s * D + i) * n + pc];
     }
-    // 32-bit step counter (the generator's counter word is 32 bits wide)
+    // 32-bit step counter (the generator's counter word is 32 bits wide);
+    // unrolled twice where the registers allow (a large fast part would spill)
+    constexpr int UNROLL = D <= 4 ? 2 : 1;
     const uint32_t mb = (uint32_t)m0, steps = (uint32_t)(m1 - m0);
-#pragma unroll 2
+#pragma unroll UNROLL
     for (uint32_t i = 0; i < steps; ++i) {
 #pragma unroll
         for (int q = 0; q < PPT; ++q)
