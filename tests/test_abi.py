@@ -95,6 +95,7 @@ def test_validation_rejects_before_launch(lib):
     assert L.pr_match_knots(p, p, 1 << 20, 4, 100, 64, p, 1024, p, p, None) == -3
     assert L.pr_parareal_knot_sorts(None) == -1
     assert L.pr_parareal_batch_knot_sorts(None, None) == -1
+    assert L.pr_parareal_batch_info(None, None, None, None, None, None) == -1
     assert L.pr_quantile_jump(p, p, p, -1, 100, p, None) == -1
     assert L.pr_quantile_jump(p, p, p, 3, 0, p, None) == -1
     assert L.pr_quantile_jump(p, p, p, 3, 2048, p, None) == -1
