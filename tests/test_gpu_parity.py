@@ -305,6 +305,7 @@ def test_restrict_many_small_segments(torch_dev, k, n):
                                            (4, 70_001, True, pr.PR_F64), (2, 2 ** 20, False, pr.PR_F64),
                                            (2, 2 ** 20, True, pr.PR_F64), (1, 2 ** 20 + 1, False, pr.PR_F64),
                                            (1, 2 ** 20 + 2 ** 17, False, pr.PR_F64),
+                                           (2, 2 ** 16, False, pr.PR_F64), (2, 2 ** 16 - 1, False, pr.PR_F64),
                                            (3, 4097, True, pr.PR_F32), (2, 2 ** 20, False, pr.PR_F32),
                                            (1, 2 ** 20 + 1, True, pr.PR_F32)])
 def test_restrict_rank_only(torch_dev, k, n, ties, prec):
@@ -312,7 +313,9 @@ def test_restrict_rank_only(torch_dev, k, n, ties, prec):
     segment they go through the staging buffer, beyond by direct stores; for
     FP64 keys the runs of hundreds of signed zeros of ties=True hand the
     ranks to the complete sort, and ensembles above 2^20 + 2^16 keys are
-    sorted by the radix passes from the start."""
+    sorted by the radix passes from the start, as are those below 2^16 (the
+    two sizes at that edge: 2^16 by splitters in 16 buckets, 2^16 - 1 by
+    radix passes)."""
     torch = torch_dev
     _say(f"restrict rank only k={k} n={n} ties={ties} precision={prec}")
     xs = inputs.slow_values(300 + n % 1000, k, n, ties=ties)
